@@ -1,0 +1,156 @@
+"""Benchmark: spin-update attempts/s of the REWL hot path on one MI355X.
+
+One step = one segment of the whole hot path for every walker: 1e4 trial
+moves per walker (Philox draws, proposal, local field, dE, bin, acceptance,
+ln g / H update), the resync when due, the flatness test with the ln f
+update, and one replica-exchange step.  Inputs are resident in HBM before
+the timed region.  Default workload: bcc L=8, four shells, 16 windows x 8
+walkers (1024 spins each), FP32 energy changes with FP64 energy/ln g.
+
+Prints ONE JSON line (see the keys at the end of main()).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+LDS_PEAK_GBS = 256 * 128 * 2.4          # 256 CUs x 128 B/clk x 2.4 GHz = 78643 GB/s
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def bytes_per_attempt(z, mode):
+    """Algorithmic LDS bytes of one trial move: z neighbour spins and the
+    site's own spin (3 components each), ln g read at the proposed bin, and
+    the ln g + H update of the current bin (read + write)."""
+    s = 12 if mode == "fp32_de" else 24
+    return z * s + s + 8 + (8 + 4) * 2
+
+
+def cpu_baseline(cfg, seconds):
+    """The oracle as it stands, on the host cores, on a bounded sample:
+    whole segments of the same workload until `seconds` have elapsed."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import oracle
+    from oracle.build import build_oracle
+    build_oracle()
+    threads = min(os.cpu_count() or 1, 64)
+    lat = cfg["lattice"]
+    o = oracle.Oracle(L=lat[1], J=lat[2])
+    o.set_windows(*cfg["windows"])
+    o.set_schedule(*cfg["schedule"])
+    o.set_threads(threads)
+    o.init(cfg["seed"])
+    W = o.W
+    seg = cfg["schedule"][4]
+    t0 = time.perf_counter()
+    segs = 0
+    while time.perf_counter() - t0 < seconds:
+        o.run(1)
+        segs += 1
+    dt = time.perf_counter() - t0
+    return {"value": segs * seg * W / dt, "unit": "attempts/s", "cores": threads, "kind": "oracle",
+            "sample": "%d segments x %d walkers x %d moves of the same workload (FP64 oracle, "
+                      "%.1f s)" % (segs, W, seg, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--mode", default="fp32_de", choices=["fp32_de", "fp64", "fp64_det"])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the REWL hot path here is single-GPU "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1411_4212_amd import workloads
+    from paper_1411_4212_amd.rewl import Run
+
+    cfg = workloads.c2()
+    lat = cfg["lattice"]
+    z = [8, 6, 12, 24, 8, 6, 24, 24]
+    zsum = sum(z[:len(lat[2])])
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    log("bench: building run", cfg["name"], args.mode)
+    r = Run([dict(lattice=lat, windows=cfg["windows"], schedule=cfg["schedule"])], mode=args.mode)
+    r.init(cfg["seed"])
+    W = r.n_walkers
+    seg = cfg["schedule"][4]
+    log("bench: warmup", args.warmup)
+    for _ in range(args.warmup):
+        r.sweep()
+        r.exchange()
+    torch.cuda.synchronize()
+    a0, _ = r.total_attempts()
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    log("bench: timed steps", args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        evs[k][0].record(stream)
+        r.sweep()
+        evs[k][1].record(stream)
+        r.exchange()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    a1, _ = r.total_attempts()
+    attempts = a1 - a0
+    wall = t1 - t0
+    sweep_ms = [s.elapsed_time(e) for s, e in evs]
+    avg_sweep_s = sum(sweep_ms) / len(sweep_ms) / 1e3
+    per_launch_bytes = bytes_per_attempt(zsum, args.mode) * W * seg
+    achieved = per_launch_bytes / avg_sweep_s / 1e9
+    log("bench: %.3e attempts/s, sweep %.3f ms avg" % (attempts / wall, avg_sweep_s * 1e3))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("bench: cpu baseline (oracle)")
+        cpu = cpu_baseline(cfg, args.cpu_seconds)
+
+    out = {
+        "metric": "spin-update attempts/s",
+        "value": attempts / wall,
+        "unit": "attempts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32_de": "f32", "fp64": "f64", "fp64_det": "f64"}[args.mode],
+        "data": "synthetic",
+        "config": {"workload": "%s: bcc L=%d (%d spins), %d shells (z=%d), %d windows x %d walkers, "
+                               "%d bins, segment %d moves/walker"
+                               % (cfg["name"], lat[1], 2 * lat[1] ** 3, len(lat[2]), zsum,
+                                  cfg["windows"][3], cfg["windows"][5], cfg["windows"][2], seg),
+                   "mode": args.mode, "walkers": W, "attempts_timed": attempts,
+                   "parallelism": "one wavefront per walker, single GPU"},
+        "roofline": {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / LDS_PEAK_GBS, "traffic": None,
+                     "kernel": "sweep_kernel<%s>" % args.mode,
+                     "bytes_per_attempt": bytes_per_attempt(zsum, args.mode),
+                     "avg_launch_ms": avg_sweep_s * 1e3},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,238 @@
+/*
+ * rewl.h -- C ABI of librewl: replica-exchange Wang-Landau (REWL) sampling of
+ * the classical Heisenberg model on MI355X (gfx950).
+ *
+ * The calls follow the paper's statement of the problem (Perera, Li,
+ * Eisenbach, Vogel, Landau, "Replica-exchange Wang-Landau sampling: pushing
+ * the limits of Monte Carlo simulations in materials sciences"):
+ *   - a Hamiltonian H = -sum_{i<j} J_ij S_i.S_j with unit spins   (Model, Eq. 1)
+ *   - a bcc lattice of L^3 cells, N = 2 L^3 spins, couplings by
+ *     neighbour shell                                             (Model)
+ *   - a restricted global range [E_min, E_max] and bin width     (Model; Sec. original WL)
+ *   - h windows overlapping by the ratio o, m walkers each        (Sec. parallel scheme)
+ *   - replica exchange between adjacent windows after a fixed
+ *     number of trial moves                                       (Sec. parallel scheme; Sec. simulation details)
+ *   - flatness fraction p and final modification factor f_min    (Sec. original WL; Sec. simulation details)
+ * and return the g~(E) fragments of every walker (Sec. parallel scheme).
+ *
+ * Conventions
+ *   - Every call returns REWL_OK (0) or a negative REWL_E* code; the text of
+ *     the last error of the calling thread is rewl_last_error().  No C++
+ *     exception crosses this interface.
+ *   - Call order: rewl_create -> rewl_add_instance + rewl_set_lattice_* +
+ *     rewl_set_windows + rewl_set_schedule for every instance ->
+ *     rewl_query_sizes -> rewl_bind_buffers -> rewl_init_walkers ->
+ *     rewl_run / rewl_exchange / rewl_poll -> rewl_read_*.  A call out of
+ *     order returns REWL_ESTATE.
+ *   - Host arrays passed in are copied during the call; the caller keeps
+ *     ownership.  Device buffers are allocated by the caller (for instance
+ *     as PyTorch tensors) with the sizes rewl_query_sizes reports, must be
+ *     256-byte aligned and must outlive the context.  The library itself
+ *     never allocates device memory.
+ *   - Work is enqueued on the HIP stream given to rewl_create.  rewl_run and
+ *     rewl_exchange return before the GPU finishes; rewl_poll, rewl_read_*
+ *     and rewl_init_walkers synchronise that stream.  A kernel fault shows up
+ *     at the next synchronising call as REWL_EDEVICE.
+ *   - Energies are in units of the couplings (k_B = 1).  Bins are global
+ *     indices on [E_min, E_max) with bin(E) = floor((E - E_min) * B /
+ *     (E_max - E_min)); windows are half-open bin ranges [lo, hi).
+ *   - Random numbers: Philox4x32-10 with key (seed, walker id) and counter
+ *     (attempt low word, attempt high word, draw, stream tag), so a run is
+ *     reproducible from its seed.
+ */
+#ifndef REWL_H
+#define REWL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rewl_ctx rewl_ctx;
+typedef int32_t rewl_status;
+
+enum {
+    REWL_OK = 0,
+    REWL_EINVAL = -1,       /* bad argument */
+    REWL_ESTATE = -2,       /* call out of order */
+    REWL_EDEVICE = -3,      /* HIP runtime error or kernel fault */
+    REWL_ERANGE = -4,       /* a size exceeds a documented limit */
+    REWL_EINIT = -5,        /* a walker could not be driven into its window */
+    REWL_ENUMERIC = -6,     /* non-finite ln g or energy detected */
+    REWL_ECORRUPT = -7,     /* reserved */
+    REWL_EUNSUPPORTED = -8  /* combination not implemented */
+};
+
+/* Arithmetic modes of the trial-move kernel.
+ *  FP64_DET  all arithmetic in FP64 in the canonical sequential order (local
+ *            field summed over the neighbour list in list order), so the
+ *            trajectory is reproducible bit for bit; spins FP64 in LDS.
+ *  FP64      FP64 spins and local field, lanes gather neighbours in
+ *            parallel and sum them with a wavefront reduction.
+ *  FP32_DE   FP32 spins, local field and energy change; the running energy,
+ *            ln g, bins and the periodic full-energy resync stay FP64.       */
+enum { REWL_MODE_FP64_DET = 0, REWL_MODE_FP64 = 1, REWL_MODE_FP32_DE = 2 };
+
+/* Device buffers the caller allocates (indices into the size/pointer arrays). */
+enum {
+    REWL_BUF_SPINS = 0,     /* configurations, one per walker              */
+    REWL_BUF_STATE = 1,     /* per-walker dynamic state                    */
+    REWL_BUF_LNG = 2,       /* ln g~ per walker window bin, FP64           */
+    REWL_BUF_HIST = 3,      /* H per walker window bin, uint32             */
+    REWL_BUF_VISITED = 4,   /* visited flag per walker window bin, uint8   */
+    REWL_BUF_PARAMS = 5,    /* read-only lattice / window tables           */
+    REWL_BUF_CONTROL = 6,   /* per-instance flags and exchange counters    */
+    REWL_NBUF = 7
+};
+
+/* Limits. */
+#define REWL_MAX_DEGREE 128          /* neighbours per site                     */
+#define REWL_MAX_SHELLS 8            /* bcc shells                               */
+#define REWL_MAX_WALKERS_PER_WINDOW 64
+#define REWL_MAX_WINDOW_BINS 4096
+
+/* Per-walker state as read back by rewl_read_walker_state. */
+typedef struct {
+    double E;                /* running energy of the configuration held     */
+    double lnf;              /* current ln f                                 */
+    double max_drift;        /* largest |E_running - E_full| seen at resync  */
+    int32_t bin;             /* global bin of E                              */
+    int32_t config;          /* index of the configuration held (in instance) */
+    int32_t iteration;       /* number of ln f halvings so far               */
+    int32_t done;            /* 1 once the iteration with ln f <= ln f_final was flat */
+    int32_t n_visited;       /* bins visited so far                          */
+    int32_t window;          /* window index                                 */
+    uint64_t attempts;       /* trial moves made                             */
+    uint64_t accepts;        /* trial moves accepted                         */
+    uint64_t rejected_outside; /* proposals outside the window or range      */
+} rewl_walker_state;
+
+/* One trial move of the per-attempt trace (rewl_set_trace). 24 bytes. */
+typedef struct {
+    uint32_t site;
+    uint32_t flags;          /* bit0 accepted, bit1 proposal outside window  */
+    double E;                /* energy after the move                        */
+    int32_t bin;             /* bin after the move                           */
+    uint32_t attempt_lo;     /* low word of the attempt number               */
+} rewl_trace_rec;
+
+/* Create a context on HIP device `device`, enqueuing on `hip_stream`
+ * (a hipStream_t; NULL = the null stream), in arithmetic mode `mode`. */
+rewl_status rewl_create(rewl_ctx **out, int32_t device, void *hip_stream, int32_t mode);
+
+/* Destroy a context (NULL-safe).  Does not free caller-owned buffers. */
+void rewl_destroy(rewl_ctx *ctx);
+
+/* Add one independent REWL run; its index is written to *instance_id_out.
+ * A context may hold many instances of different sizes (batched runs). */
+rewl_status rewl_add_instance(rewl_ctx *ctx, int32_t *instance_id_out);
+
+/* Periodic bcc lattice of L^3 cells (N = 2 L^3 spins, Model section) with
+ * couplings J[n] on the n-th neighbour shell, n < n_shells <= 8; shell n
+ * holds the lattice vectors of the n-th smallest length.  Site index
+ * ((s L + z) L + y) L + x for sublattice s and cell (x, y, z).  Requires
+ * that no two neighbours of a site coincide under the periodic wrap. */
+rewl_status rewl_set_lattice_bcc(rewl_ctx *ctx, int32_t inst, int32_t L, int32_t n_shells,
+                                 const double *J);
+
+/* Arbitrary couplings (Model, Eq. 1): pair p couples spins i[p] and j[p]
+ * with J[p]; each site's neighbour list is built in pair order.  Intended for
+ * small test systems (spins read from global memory for the neighbours). */
+rewl_status rewl_set_couplings_explicit(rewl_ctx *ctx, int32_t inst, int32_t N, int64_t n_pairs,
+                                        const int32_t *i, const int32_t *j, const double *J);
+
+/* Global range [E_min, E_max) on n_global_bins bins, split into n_windows
+ * windows of equal width overlapping by the ratio `overlap` (parallel
+ * scheme): w = round(B / (1 + (h-1)(1-o))) bins per window, window k starts
+ * at round(k (B - w)/(h - 1)), round(x) = floor(x + 1/2).  Each window holds
+ * walkers_per_window walkers. */
+rewl_status rewl_set_windows(rewl_ctx *ctx, int32_t inst, double E_min, double E_max,
+                             int32_t n_global_bins, int32_t n_windows, double overlap,
+                             int32_t walkers_per_window);
+
+/* Wang-Landau schedule (Sec. original WL): flat iff min H >= (flat_num /
+ * flat_den) <H> over visited bins; ln f starts at lnf_init and halves on every
+ * flat histogram; a walker is done when the iteration with ln f <= lnf_final
+ * is flat.  exchange_interval trial moves per walker form one segment; the
+ * flatness test and one replica-exchange step follow every segment.  The
+ * energy is recomputed from scratch at the end of every segment in which the
+ * walker's attempt count crosses a multiple of resync_interval (0 = never). */
+rewl_status rewl_set_schedule(rewl_ctx *ctx, int32_t inst, int32_t flat_num, int32_t flat_den,
+                              double lnf_init, double lnf_final, int64_t exchange_interval,
+                              int64_t resync_interval);
+
+/* Byte sizes of the REWL_NBUF device buffers the caller must provide. */
+rewl_status rewl_query_sizes(rewl_ctx *ctx, size_t *bytes_out /* [REWL_NBUF] */);
+
+/* Hand the library its device buffers (caller-owned, 256-byte aligned) and
+ * upload the read-only tables.  Synchronises the stream. */
+rewl_status rewl_bind_buffers(rewl_ctx *ctx, void *const *dev_ptrs /* [REWL_NBUF] */);
+
+/* Start every walker: ln g~ = 0, H = 0, ln f = lnf_init (Sec. original WL);
+ * configuration = init_spins (N*3 doubles per instance, concatenated in
+ * instance order) or, if NULL, every spin uniform on the sphere; then each
+ * walker is driven into its window by moves accepted when they enter the
+ * window or come strictly closer to it (at most 10^4 N moves, else
+ * REWL_EINIT).  Synchronises the stream. */
+rewl_status rewl_init_walkers(rewl_ctx *ctx, uint64_t seed, const double *init_spins);
+
+/* Enqueue n_segments segments: exchange_interval trial moves per walker,
+ * the resync when due and the flatness test, then one replica-exchange step
+ * (Sec. parallel scheme).  Instances whose walkers are all done are skipped.
+ * Asynchronous. */
+rewl_status rewl_run(rewl_ctx *ctx, int64_t n_segments);
+
+/* Enqueue the trial-move part of one segment only: exchange_interval trial
+ * moves per walker, the resync when due and the flatness test, without the
+ * exchange step (rewl_run = rewl_sweep + rewl_exchange, repeated).
+ * Asynchronous. */
+rewl_status rewl_sweep(rewl_ctx *ctx);
+
+/* Enqueue one replica-exchange step on its own.  Asynchronous. */
+rewl_status rewl_exchange(rewl_ctx *ctx);
+
+/* Synchronise and report whether every instance is done. */
+rewl_status rewl_poll(rewl_ctx *ctx, int32_t *all_done_out);
+
+/* Read-out (synchronising).  inst = instance, walker = index within it
+ * (walker w belongs to window w / m).  rewl_read_lng / rewl_read_hist /
+ * rewl_read_visited copy min(cap, hi - lo) entries of the walker's window
+ * and return that count through *n_out. */
+rewl_status rewl_read_lng(rewl_ctx *ctx, int32_t inst, int32_t walker, double *out, int32_t cap,
+                          int32_t *n_out);
+rewl_status rewl_read_hist(rewl_ctx *ctx, int32_t inst, int32_t walker, uint32_t *out,
+                           int32_t cap, int32_t *n_out);
+rewl_status rewl_read_visited(rewl_ctx *ctx, int32_t inst, int32_t walker, uint8_t *out,
+                              int32_t cap, int32_t *n_out);
+rewl_status rewl_read_walker_state(rewl_ctx *ctx, int32_t inst, int32_t walker,
+                                   rewl_walker_state *out);
+/* configuration `config` of instance inst as N*3 doubles */
+rewl_status rewl_read_config(rewl_ctx *ctx, int32_t inst, int32_t config, double *out,
+                             int64_t cap);
+rewl_status rewl_read_window(rewl_ctx *ctx, int32_t inst, int32_t win, int32_t *lo_bin,
+                             int32_t *hi_bin);
+/* exchange attempts / accepts of the window pairs (k, k+1), k < h-1 */
+rewl_status rewl_read_exchange_stats(rewl_ctx *ctx, int32_t inst, uint64_t *attempts,
+                                     uint64_t *accepts, int32_t cap);
+/* number of exchange steps made so far */
+rewl_status rewl_read_step(rewl_ctx *ctx, int64_t *step_out);
+
+/* Record the first `capacity` trial moves of every walker into the device
+ * buffer dev_records (caller-owned, capacity * total walkers records of
+ * rewl_trace_rec, walker-major in instance order); NULL switches recording
+ * off.  Call before rewl_init_walkers. */
+rewl_status rewl_set_trace(rewl_ctx *ctx, void *dev_records, int64_t capacity);
+
+/* Totals over all walkers of the context (synchronising). */
+rewl_status rewl_total_attempts(rewl_ctx *ctx, uint64_t *attempts, uint64_t *accepts);
+
+/* Human-readable text of the calling thread's last error. */
+const char *rewl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* REWL_H */

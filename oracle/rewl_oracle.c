@@ -773,6 +773,9 @@ static void exchange_step(octx *c)
             if (!in_window(c, b->E, a->lo, a->hi, &bb_in_a)) continue;
             /* each walker's estimate must exist at the energy it receives */
             if (!b->vis[ba_in_b - b->lo] || !a->vis[bb_in_a - a->lo]) continue;
+            /* the stored bins (which a resync may have clamped) must lie in
+             * the other window too */
+            if (a->bin < b->lo || a->bin >= b->hi || b->bin < a->lo || b->bin >= a->hi) continue;
             uint32_t rr[4];
             draw(c->seed, c->instance, t, ((uint32_t)k << 16) | (uint32_t)r, TAG_EXCH, rr);
             double u = u53(rr[0], rr[1]);

@@ -1,0 +1,752 @@
+// rewl_api.cpp -- host side of librewl: configuration, validation, device
+// buffer layout, kernel launches and read-out.  See include/rewl.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rewl_internal.h"
+
+using namespace rewl;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+rewl_status fail(rewl_status code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(REWL_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+struct InstanceCfg {
+    bool has_lattice = false, has_windows = false, has_schedule = false;
+    int32_t lattice = LAT_BCC;
+    int32_t L = 0, N = 0;
+    std::vector<double> Jshell;
+    std::vector<int32_t> pi, pj;
+    std::vector<double> pJ;
+    double Emin = 0, Emax = 0, overlap = 0;
+    int32_t B = 0, h = 0, m = 0;
+    int32_t flat_num = 0, flat_den = 1;
+    double lnf_init = 1.0, lnf_final = 1e-8;
+    int64_t seg = 0, resync = 0;
+    // derived
+    int32_t z = 0;
+    std::vector<int32_t> lo, hi;
+};
+
+int round_half_up(double x) { return (int)std::floor(x + 0.5); }
+
+// bcc lattice vectors in half-cell units (integer triples of equal parity),
+// grouped in shells of increasing length, lexicographic within a shell.
+struct ShellVec {
+    int dx, dy, dz, shell;
+};
+
+std::vector<ShellVec> bcc_shell_vectors(int n_shells)
+{
+    std::vector<std::array<int, 4>> all;   // d2, dx, dy, dz
+    for (int a = -5; a <= 5; ++a)
+        for (int b = -5; b <= 5; ++b)
+            for (int c = -5; c <= 5; ++c) {
+                if (a == 0 && b == 0 && c == 0) continue;
+                if ((a & 1) != (b & 1) || (a & 1) != (c & 1)) continue;
+                all.push_back({a * a + b * b + c * c, a, b, c});
+            }
+    std::sort(all.begin(), all.end());
+    std::vector<ShellVec> out;
+    int shell = -1, last_d2 = -1;
+    for (const auto &v : all) {
+        if (v[0] != last_d2) {
+            ++shell;
+            last_d2 = v[0];
+        }
+        if (shell >= n_shells) break;
+        out.push_back({v[1], v[2], v[3], shell});
+    }
+    return out;
+}
+
+}  // namespace
+
+struct rewl_ctx {
+    int32_t device = 0;
+    hipStream_t stream = nullptr;
+    int32_t mode = 0;
+    std::vector<InstanceCfg> inst;
+    int stage = 0;   // 0 configuring, 1 sized, 2 bound, 3 initialised
+    size_t sizes[REWL_NBUF] = {};
+    void *buf[REWL_NBUF] = {};
+    // host copies of the tables
+    std::vector<InstDesc> idesc;
+    std::vector<WalkerDesc> wdesc;
+    std::vector<BccSlot> slots;
+    std::vector<int32_t> tdeg, tnbr;
+    std::vector<double> tJ;
+    std::vector<double> init_host;
+    // PARAMS layout (byte offsets)
+    size_t off_inst = 0, off_wdesc = 0, off_slots = 0, off_tdeg = 0, off_tnbr = 0, off_tJ = 0,
+           off_init = 0;
+    // CONTROL layout
+    size_t off_ictl = 0, off_xatt = 0, off_xacc = 0;
+    int32_t n_walkers = 0, n_xstat = 0;
+    int64_t total_bins = 0, total_spins = 0;
+    int32_t lds_spins_bytes = 0, lds_bins = 0;
+    size_t lds_per_walker = 0;
+    int32_t wpb = 1;
+    uint32_t seed = 0;
+    int64_t t = 0;
+    rewl_trace_rec *trace = nullptr;
+    int64_t trace_cap = 0;
+};
+
+namespace {
+
+size_t spin_bytes(int mode) { return mode == REWL_MODE_FP32_DE ? 16 : 32; }
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+rewl_status check_inst(rewl_ctx *c, int32_t inst)
+{
+    if (!c) return fail(REWL_EINVAL, "null context");
+    if (inst < 0 || inst >= (int32_t)c->inst.size()) return fail(REWL_EINVAL, "bad instance index");
+    if (c->stage != 0) return fail(REWL_ESTATE, "instances can only be configured before rewl_query_sizes");
+    return REWL_OK;
+}
+
+KArgs make_args(rewl_ctx *c)
+{
+    KArgs a{};
+    unsigned char *P = (unsigned char *)c->buf[REWL_BUF_PARAMS];
+    unsigned char *Cb = (unsigned char *)c->buf[REWL_BUF_CONTROL];
+    a.spins = c->buf[REWL_BUF_SPINS];
+    a.state = (WalkerState *)c->buf[REWL_BUF_STATE];
+    a.lng = (double *)c->buf[REWL_BUF_LNG];
+    a.hist = (uint32_t *)c->buf[REWL_BUF_HIST];
+    a.vis = (uint8_t *)c->buf[REWL_BUF_VISITED];
+    a.inst = (const InstDesc *)(P + c->off_inst);
+    a.wdesc = (const WalkerDesc *)(P + c->off_wdesc);
+    a.slots = c->slots.empty() ? nullptr : (const BccSlot *)(P + c->off_slots);
+    a.tdeg = c->tdeg.empty() ? nullptr : (const int32_t *)(P + c->off_tdeg);
+    a.tnbr = c->tnbr.empty() ? nullptr : (const int32_t *)(P + c->off_tnbr);
+    a.tJ = c->tJ.empty() ? nullptr : (const double *)(P + c->off_tJ);
+    a.init_spins = c->init_host.empty() ? nullptr : (const double *)(P + c->off_init);
+    a.ictl = (InstControl *)(Cb + c->off_ictl);
+    a.xatt = (unsigned long long *)(Cb + c->off_xatt);
+    a.xacc = (unsigned long long *)(Cb + c->off_xacc);
+    a.trace = c->trace;
+    a.trace_cap = c->trace_cap;
+    a.t = c->t;
+    a.seed = c->seed;
+    a.n_walkers = c->n_walkers;
+    a.n_inst = (int32_t)c->inst.size();
+    a.walkers_per_block = c->wpb;
+    a.lds_spins_bytes = c->lds_spins_bytes;
+    a.lds_bins = c->lds_bins;
+    return a;
+}
+
+// Build the read-only tables and compute buffer sizes.
+rewl_status finalize(rewl_ctx *c)
+{
+    if (c->inst.empty()) return fail(REWL_ESTATE, "no instance added");
+    c->idesc.clear();
+    c->wdesc.clear();
+    c->slots.clear();
+    c->tdeg.clear();
+    c->tnbr.clear();
+    c->tJ.clear();
+    int64_t bin_off = 0, cfg_off = 0;
+    int32_t walker_base = 0, xstat = 0;
+    int32_t max_N = 0, max_nb = 0;
+    for (size_t ii = 0; ii < c->inst.size(); ++ii) {
+        InstanceCfg &q = c->inst[ii];
+        if (!q.has_lattice || !q.has_windows || !q.has_schedule)
+            return fail(REWL_ESTATE, "instance " + std::to_string(ii) +
+                                         " needs lattice, windows and schedule");
+        InstDesc d{};
+        d.N = q.N;
+        d.L = q.L;
+        d.lattice = q.lattice;
+        d.h = q.h;
+        d.m = q.m;
+        d.B = q.B;
+        d.walker_base = walker_base;
+        d.n_walkers = q.h * q.m;
+        d.flat_num = q.flat_num;
+        d.flat_den = q.flat_den;
+        d.xstat_off = xstat;
+        d.Emin = q.Emin;
+        d.inv_de = (double)q.B / (q.Emax - q.Emin);
+        d.lnf_final = q.lnf_final;
+        d.lnf_init = q.lnf_init;
+        d.seg_len = q.seg;
+        d.resync = q.resync;
+        d.cfg_off = cfg_off;
+        d.init_off = -1;
+        if (q.lattice == LAT_BCC) {
+            std::vector<ShellVec> v = bcc_shell_vectors((int)q.Jshell.size());
+            d.z = (int32_t)v.size();
+            d.slot_off = (int32_t)c->slots.size();
+            // every neighbour of a site must be a distinct other site
+            std::vector<int> seen;
+            for (int s = 0; s < 2; ++s) {
+                seen.clear();
+                for (const ShellVec &sv : v) {
+                    const int t = s ^ (sv.dx & 1);
+                    auto w = [&](int base, int dd) {
+                        int x = (base + (s + dd - t) / 2) % q.L;
+                        return x < 0 ? x + q.L : x;
+                    };
+                    const int idx = ((t * q.L + w(0, sv.dz)) * q.L + w(0, sv.dy)) * q.L + w(0, sv.dx);
+                    if (idx == s * q.L * q.L * q.L) return fail(REWL_EINVAL, "lattice too small: a neighbour wraps onto the site");
+                    if (std::find(seen.begin(), seen.end(), idx) != seen.end())
+                        return fail(REWL_EINVAL, "lattice too small: two neighbours coincide under the periodic wrap");
+                    seen.push_back(idx);
+                }
+            }
+            for (const ShellVec &sv : v) {
+                BccSlot sl{};
+                const int dd[3] = {sv.dx, sv.dy, sv.dz};
+                for (int s = 0; s < 2; ++s) {
+                    const int t = s ^ (sv.dx & 1);
+                    for (int k = 0; k < 3; ++k) sl.d[s][k] = (int8_t)((s + dd[k] - t) / 2);
+                }
+                sl.flip = (uint8_t)(sv.dx & 1);
+                sl.Jd = q.Jshell[sv.shell];
+                sl.Jf = (float)sl.Jd;
+                c->slots.push_back(sl);
+            }
+        } else {
+            std::vector<int32_t> deg(q.N, 0);
+            for (size_t p = 0; p < q.pi.size(); ++p) {
+                deg[q.pi[p]]++;
+                deg[q.pj[p]]++;
+            }
+            int zmax = 1;
+            for (int i = 0; i < q.N; ++i) zmax = std::max(zmax, deg[i]);
+            if (zmax > REWL_MAX_DEGREE) return fail(REWL_ERANGE, "a site has more than 128 neighbours");
+            d.z = zmax;
+            d.tab_off = (int64_t)c->tnbr.size();
+            d.deg_off = (int32_t)c->tdeg.size();
+            const size_t base = c->tnbr.size();
+            c->tnbr.resize(base + (size_t)q.N * zmax, 0);
+            c->tJ.resize(base + (size_t)q.N * zmax, 0.0);
+            std::vector<int32_t> fill(q.N, 0);
+            for (size_t p = 0; p < q.pi.size(); ++p) {
+                const int a = q.pi[p], b = q.pj[p];
+                c->tnbr[base + (size_t)a * zmax + fill[a]] = b;
+                c->tJ[base + (size_t)a * zmax + fill[a]] = q.pJ[p];
+                fill[a]++;
+                c->tnbr[base + (size_t)b * zmax + fill[b]] = a;
+                c->tJ[base + (size_t)b * zmax + fill[b]] = q.pJ[p];
+                fill[b]++;
+            }
+            c->tdeg.insert(c->tdeg.end(), deg.begin(), deg.end());
+        }
+        if (d.z > REWL_MAX_DEGREE) return fail(REWL_ERANGE, "more than 128 neighbours per site");
+        // windows
+        q.lo.assign(q.h, 0);
+        q.hi.assign(q.h, 0);
+        int wb = round_half_up((double)q.B / (1.0 + (double)(q.h - 1) * (1.0 - q.overlap)));
+        wb = std::max(1, std::min(wb, q.B));
+        int nb_max = 0;
+        for (int k = 0; k < q.h; ++k) {
+            const int l = q.h == 1 ? 0 : round_half_up((double)k * (double)(q.B - wb) / (double)(q.h - 1));
+            q.lo[k] = l;
+            q.hi[k] = l + wb;
+            nb_max = std::max(nb_max, wb);
+        }
+        if (nb_max > REWL_MAX_WINDOW_BINS) return fail(REWL_ERANGE, "more than 4096 bins per window");
+        d.nb_max = nb_max;
+        for (int k = 0; k < q.h; ++k)
+            for (int r = 0; r < q.m; ++r) {
+                WalkerDesc wd{};
+                wd.inst = (int32_t)ii;
+                wd.win = k;
+                wd.lo = q.lo[k];
+                wd.hi = q.hi[k];
+                wd.bin_off = bin_off;
+                wd.stream = (uint32_t)(walker_base + k * q.m + r);
+                wd.local = k * q.m + r;
+                bin_off += wd.hi - wd.lo;
+                c->wdesc.push_back(wd);
+            }
+        walker_base += q.h * q.m;
+        xstat += std::max(q.h - 1, 1);
+        cfg_off += (int64_t)q.N * q.h * q.m;
+        max_N = std::max(max_N, q.N);
+        max_nb = std::max(max_nb, nb_max);
+        c->idesc.push_back(d);
+    }
+    // lattice-table offsets of the degree array: fix up after the loop
+    c->n_walkers = walker_base;
+    c->n_xstat = xstat;
+    c->total_bins = bin_off;
+    c->total_spins = cfg_off;
+    c->lds_spins_bytes = (int32_t)(((size_t)max_N * spin_bytes(c->mode) + 15) & ~(size_t)15);
+    c->lds_bins = (max_nb + 15) & ~15;
+    c->lds_per_walker = (size_t)c->lds_spins_bytes + (size_t)c->lds_bins * 13u;
+    if (c->lds_per_walker > 160 * 1024)
+        return fail(REWL_EUNSUPPORTED, "configuration plus window does not fit in 160 KB of LDS");
+    c->wpb = 1;
+
+    size_t o = 0;
+    c->off_inst = o;
+    o = align256(o + sizeof(InstDesc) * c->idesc.size());
+    c->off_wdesc = o;
+    o = align256(o + sizeof(WalkerDesc) * c->wdesc.size());
+    c->off_slots = o;
+    o = align256(o + sizeof(BccSlot) * c->slots.size());
+    c->off_tdeg = o;
+    o = align256(o + sizeof(int32_t) * c->tdeg.size());
+    c->off_tnbr = o;
+    o = align256(o + sizeof(int32_t) * c->tnbr.size());
+    c->off_tJ = o;
+    o = align256(o + sizeof(double) * c->tJ.size());
+    c->off_init = o;
+    int64_t init_doubles = 0;
+    for (auto &q : c->inst) init_doubles += 3 * (int64_t)q.N;
+    o = align256(o + sizeof(double) * (size_t)init_doubles);
+    c->sizes[REWL_BUF_PARAMS] = std::max<size_t>(o, 256);
+
+    c->sizes[REWL_BUF_SPINS] = align256(spin_bytes(c->mode) * (size_t)c->total_spins);
+    c->sizes[REWL_BUF_STATE] = align256(sizeof(WalkerState) * (size_t)c->n_walkers);
+    c->sizes[REWL_BUF_LNG] = align256(sizeof(double) * (size_t)c->total_bins);
+    c->sizes[REWL_BUF_HIST] = align256(sizeof(uint32_t) * (size_t)c->total_bins);
+    c->sizes[REWL_BUF_VISITED] = align256((size_t)c->total_bins);
+    size_t oc = 0;
+    c->off_ictl = oc;
+    oc = align256(oc + sizeof(InstControl) * c->inst.size());
+    c->off_xatt = oc;
+    oc = align256(oc + sizeof(unsigned long long) * (size_t)c->n_xstat);
+    c->off_xacc = oc;
+    oc = align256(oc + sizeof(unsigned long long) * (size_t)c->n_xstat);
+    c->sizes[REWL_BUF_CONTROL] = oc;
+    return REWL_OK;
+}
+
+rewl_status sync_check(rewl_ctx *c)
+{
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail(REWL_EDEVICE, std::string("stream: ") + hipGetErrorString(e));
+    return REWL_OK;
+}
+
+rewl_status check_walker(rewl_ctx *c, int32_t inst, int32_t walker, int *gw)
+{
+    if (!c) return fail(REWL_EINVAL, "null context");
+    if (c->stage < 3) return fail(REWL_ESTATE, "walkers not initialised");
+    if (inst < 0 || inst >= (int32_t)c->inst.size()) return fail(REWL_EINVAL, "bad instance index");
+    const InstDesc &d = c->idesc[inst];
+    if (walker < 0 || walker >= d.n_walkers) return fail(REWL_EINVAL, "bad walker index");
+    *gw = d.walker_base + walker;
+    return REWL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *rewl_last_error(void) { return g_last_error.c_str(); }
+
+rewl_status rewl_create(rewl_ctx **out, int32_t device, void *hip_stream, int32_t mode)
+{
+    if (!out) return fail(REWL_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (mode < REWL_MODE_FP64_DET || mode > REWL_MODE_FP32_DE) return fail(REWL_EINVAL, "unknown mode");
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(REWL_EINVAL, "bad device index");
+    rewl_ctx *c = new (std::nothrow) rewl_ctx();
+    if (!c) return fail(REWL_EINVAL, "out of host memory");
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->mode = mode;
+    *out = c;
+    return REWL_OK;
+}
+
+void rewl_destroy(rewl_ctx *ctx) { delete ctx; }
+
+rewl_status rewl_add_instance(rewl_ctx *ctx, int32_t *instance_id_out)
+{
+    if (!ctx || !instance_id_out) return fail(REWL_EINVAL, "null argument");
+    if (ctx->stage != 0) return fail(REWL_ESTATE, "cannot add instances after rewl_query_sizes");
+    ctx->inst.emplace_back();
+    *instance_id_out = (int32_t)ctx->inst.size() - 1;
+    return REWL_OK;
+}
+
+rewl_status rewl_set_lattice_bcc(rewl_ctx *ctx, int32_t inst, int32_t L, int32_t n_shells, const double *J)
+{
+    rewl_status st = check_inst(ctx, inst);
+    if (st) return st;
+    if (L < 2 || L > 256) return fail(REWL_EINVAL, "L must be in [2, 256]");
+    if (n_shells < 1 || n_shells > REWL_MAX_SHELLS || !J) return fail(REWL_EINVAL, "1..8 shells with couplings required");
+    for (int i = 0; i < n_shells; ++i)
+        if (!std::isfinite(J[i])) return fail(REWL_EINVAL, "non-finite coupling");
+    const int64_t N = 2ll * L * L * L;
+    if (N > (1 << 22)) return fail(REWL_ERANGE, "too many sites");
+    InstanceCfg &q = ctx->inst[inst];
+    q.lattice = LAT_BCC;
+    q.L = L;
+    q.N = (int32_t)N;
+    q.Jshell.assign(J, J + n_shells);
+    q.has_lattice = true;
+    return REWL_OK;
+}
+
+rewl_status rewl_set_couplings_explicit(rewl_ctx *ctx, int32_t inst, int32_t N, int64_t n_pairs,
+                                        const int32_t *i, const int32_t *j, const double *J)
+{
+    rewl_status st = check_inst(ctx, inst);
+    if (st) return st;
+    if (N < 1 || N > (1 << 22)) return fail(REWL_EINVAL, "N out of range");
+    if (n_pairs < 0 || (n_pairs > 0 && (!i || !j || !J))) return fail(REWL_EINVAL, "bad pair arrays");
+    for (int64_t p = 0; p < n_pairs; ++p) {
+        if (i[p] < 0 || i[p] >= N || j[p] < 0 || j[p] >= N || i[p] == j[p])
+            return fail(REWL_EINVAL, "pair index out of range or self-coupling");
+        if (!std::isfinite(J[p])) return fail(REWL_EINVAL, "non-finite coupling");
+    }
+    InstanceCfg &q = ctx->inst[inst];
+    q.lattice = LAT_TABLE;
+    q.L = 0;
+    q.N = N;
+    q.pi.assign(i, i + n_pairs);
+    q.pj.assign(j, j + n_pairs);
+    q.pJ.assign(J, J + n_pairs);
+    q.has_lattice = true;
+    return REWL_OK;
+}
+
+rewl_status rewl_set_windows(rewl_ctx *ctx, int32_t inst, double E_min, double E_max,
+                             int32_t n_global_bins, int32_t n_windows, double overlap,
+                             int32_t walkers_per_window)
+{
+    rewl_status st = check_inst(ctx, inst);
+    if (st) return st;
+    if (!std::isfinite(E_min) || !std::isfinite(E_max) || !(E_max > E_min))
+        return fail(REWL_EINVAL, "need finite E_min < E_max");
+    if (n_global_bins < 1 || n_windows < 1 || walkers_per_window < 1)
+        return fail(REWL_EINVAL, "bins, windows and walkers must be positive");
+    if (walkers_per_window > REWL_MAX_WALKERS_PER_WINDOW) return fail(REWL_ERANGE, "more than 64 walkers per window");
+    if (n_windows > 65535) return fail(REWL_ERANGE, "more than 65535 windows");
+    if (!(overlap >= 0.0) || !(overlap < 1.0)) return fail(REWL_EINVAL, "overlap must be in [0, 1)");
+    InstanceCfg &q = ctx->inst[inst];
+    q.Emin = E_min;
+    q.Emax = E_max;
+    q.B = n_global_bins;
+    q.h = n_windows;
+    q.overlap = overlap;
+    q.m = walkers_per_window;
+    q.has_windows = true;
+    return REWL_OK;
+}
+
+rewl_status rewl_set_schedule(rewl_ctx *ctx, int32_t inst, int32_t flat_num, int32_t flat_den,
+                              double lnf_init, double lnf_final, int64_t exchange_interval,
+                              int64_t resync_interval)
+{
+    rewl_status st = check_inst(ctx, inst);
+    if (st) return st;
+    if (flat_den < 1 || flat_num < 0 || flat_num > flat_den) return fail(REWL_EINVAL, "need 0 <= flat_num <= flat_den, flat_den >= 1");
+    if (!(lnf_init > 0.0) || !(lnf_final > 0.0) || !std::isfinite(lnf_init)) return fail(REWL_EINVAL, "ln f values must be positive");
+    if (exchange_interval < 1 || resync_interval < 0) return fail(REWL_EINVAL, "bad intervals");
+    InstanceCfg &q = ctx->inst[inst];
+    q.flat_num = flat_num;
+    q.flat_den = flat_den;
+    q.lnf_init = lnf_init;
+    q.lnf_final = lnf_final;
+    q.seg = exchange_interval;
+    q.resync = resync_interval;
+    q.has_schedule = true;
+    return REWL_OK;
+}
+
+rewl_status rewl_query_sizes(rewl_ctx *ctx, size_t *bytes_out)
+{
+    if (!ctx || !bytes_out) return fail(REWL_EINVAL, "null argument");
+    if (ctx->stage == 0) {
+        rewl_status st = finalize(ctx);
+        if (st) return st;
+        ctx->stage = 1;
+    }
+    for (int b = 0; b < REWL_NBUF; ++b) bytes_out[b] = ctx->sizes[b];
+    return REWL_OK;
+}
+
+rewl_status rewl_bind_buffers(rewl_ctx *ctx, void *const *dev_ptrs)
+{
+    if (!ctx || !dev_ptrs) return fail(REWL_EINVAL, "null argument");
+    if (ctx->stage < 1) return fail(REWL_ESTATE, "call rewl_query_sizes first");
+    for (int b = 0; b < REWL_NBUF; ++b) {
+        if (!dev_ptrs[b]) return fail(REWL_EINVAL, "null device buffer " + std::to_string(b));
+        if (((uintptr_t)dev_ptrs[b]) & 255) return fail(REWL_EINVAL, "device buffer not 256-byte aligned");
+        ctx->buf[b] = dev_ptrs[b];
+    }
+    ctx->stage = 2;
+    return REWL_OK;
+}
+
+rewl_status rewl_set_trace(rewl_ctx *ctx, void *dev_records, int64_t capacity)
+{
+    if (!ctx) return fail(REWL_EINVAL, "null context");
+    if (capacity < 0) return fail(REWL_EINVAL, "negative capacity");
+    ctx->trace = (rewl_trace_rec *)dev_records;
+    ctx->trace_cap = dev_records ? capacity : 0;
+    return REWL_OK;
+}
+
+rewl_status rewl_init_walkers(rewl_ctx *ctx, uint64_t seed, const double *init_spins)
+{
+    if (!ctx) return fail(REWL_EINVAL, "null context");
+    if (ctx->stage < 2) return fail(REWL_ESTATE, "bind buffers first");
+    HIP_TRY(hipSetDevice(ctx->device));
+    ctx->seed = (uint32_t)seed;
+    ctx->t = 0;
+    ctx->init_host.clear();
+    int64_t off = 0;
+    for (size_t ii = 0; ii < ctx->inst.size(); ++ii) {
+        const int N = ctx->inst[ii].N;
+        if (init_spins) {
+            for (int64_t k = 0; k < 3 * (int64_t)N; ++k) {
+                const double v = init_spins[off + k];
+                if (!std::isfinite(v)) return fail(REWL_EINVAL, "non-finite initial spin");
+                ctx->init_host.push_back(v);
+            }
+            ctx->idesc[ii].init_off = off;
+        } else {
+            ctx->idesc[ii].init_off = -1;
+        }
+        off += 3 * (int64_t)N;
+    }
+    unsigned char *P = (unsigned char *)ctx->buf[REWL_BUF_PARAMS];
+    hipStream_t s = ctx->stream;
+    HIP_TRY(hipMemcpyAsync(P + ctx->off_inst, ctx->idesc.data(), sizeof(InstDesc) * ctx->idesc.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(P + ctx->off_wdesc, ctx->wdesc.data(), sizeof(WalkerDesc) * ctx->wdesc.size(), hipMemcpyHostToDevice, s));
+    if (!ctx->slots.empty())
+        HIP_TRY(hipMemcpyAsync(P + ctx->off_slots, ctx->slots.data(), sizeof(BccSlot) * ctx->slots.size(), hipMemcpyHostToDevice, s));
+    if (!ctx->tdeg.empty())
+        HIP_TRY(hipMemcpyAsync(P + ctx->off_tdeg, ctx->tdeg.data(), sizeof(int32_t) * ctx->tdeg.size(), hipMemcpyHostToDevice, s));
+    if (!ctx->tnbr.empty()) {
+        HIP_TRY(hipMemcpyAsync(P + ctx->off_tnbr, ctx->tnbr.data(), sizeof(int32_t) * ctx->tnbr.size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(P + ctx->off_tJ, ctx->tJ.data(), sizeof(double) * ctx->tJ.size(), hipMemcpyHostToDevice, s));
+    }
+    if (!ctx->init_host.empty())
+        HIP_TRY(hipMemcpyAsync(P + ctx->off_init, ctx->init_host.data(), sizeof(double) * ctx->init_host.size(), hipMemcpyHostToDevice, s));
+    for (int b : {REWL_BUF_STATE, REWL_BUF_LNG, REWL_BUF_HIST, REWL_BUF_VISITED, REWL_BUF_CONTROL})
+        HIP_TRY(hipMemsetAsync(ctx->buf[b], 0, ctx->sizes[b], s));
+    KArgs a = make_args(ctx);
+    int rc = launch_init(a, ctx->mode, s, ctx->lds_per_walker);
+    if (rc) return fail(rc, "init kernel launch failed");
+    rewl_status st = sync_check(ctx);
+    if (st) return st;
+    std::vector<WalkerState> ws(ctx->n_walkers);
+    HIP_TRY(hipMemcpy(ws.data(), ctx->buf[REWL_BUF_STATE], sizeof(WalkerState) * ws.size(), hipMemcpyDeviceToHost));
+    for (int w = 0; w < ctx->n_walkers; ++w)
+        if (ws[w].status != 0)
+            return fail(REWL_EINIT, "walker " + std::to_string(w) + " could not be driven into its window");
+    ctx->stage = 3;
+    return REWL_OK;
+}
+
+rewl_status rewl_run(rewl_ctx *ctx, int64_t n_segments)
+{
+    if (!ctx) return fail(REWL_EINVAL, "null context");
+    if (ctx->stage < 3) return fail(REWL_ESTATE, "initialise walkers first");
+    if (n_segments < 0) return fail(REWL_EINVAL, "negative segment count");
+    for (int64_t k = 0; k < n_segments; ++k) {
+        KArgs a = make_args(ctx);
+        int rc = launch_sweep(a, ctx->mode, ctx->stream, ctx->lds_per_walker);
+        if (rc) return fail(rc, "sweep kernel launch failed");
+        rc = launch_exchange(a, ctx->stream);
+        if (rc) return fail(rc, "exchange kernel launch failed");
+        ctx->t += 1;
+    }
+    return REWL_OK;
+}
+
+rewl_status rewl_sweep(rewl_ctx *ctx)
+{
+    if (!ctx) return fail(REWL_EINVAL, "null context");
+    if (ctx->stage < 3) return fail(REWL_ESTATE, "initialise walkers first");
+    KArgs a = make_args(ctx);
+    int rc = launch_sweep(a, ctx->mode, ctx->stream, ctx->lds_per_walker);
+    if (rc) return fail(rc, "sweep kernel launch failed");
+    return REWL_OK;
+}
+
+rewl_status rewl_exchange(rewl_ctx *ctx)
+{
+    if (!ctx) return fail(REWL_EINVAL, "null context");
+    if (ctx->stage < 3) return fail(REWL_ESTATE, "initialise walkers first");
+    KArgs a = make_args(ctx);
+    int rc = launch_exchange(a, ctx->stream);
+    if (rc) return fail(rc, "exchange kernel launch failed");
+    ctx->t += 1;
+    return REWL_OK;
+}
+
+rewl_status rewl_poll(rewl_ctx *ctx, int32_t *all_done_out)
+{
+    if (!ctx || !all_done_out) return fail(REWL_EINVAL, "null argument");
+    if (ctx->stage < 3) return fail(REWL_ESTATE, "initialise walkers first");
+    rewl_status st = sync_check(ctx);
+    if (st) return st;
+    std::vector<InstControl> ic(ctx->inst.size());
+    HIP_TRY(hipMemcpy(ic.data(), (unsigned char *)ctx->buf[REWL_BUF_CONTROL] + ctx->off_ictl,
+                      sizeof(InstControl) * ic.size(), hipMemcpyDeviceToHost));
+    int all = 1;
+    for (auto &x : ic) all &= (x.done != 0);
+    *all_done_out = all;
+    return REWL_OK;
+}
+
+static rewl_status read_bins(rewl_ctx *ctx, int32_t inst, int32_t walker, int buf, size_t esz,
+                             void *out, int32_t cap, int32_t *n_out)
+{
+    int gw;
+    rewl_status st = check_walker(ctx, inst, walker, &gw);
+    if (st) return st;
+    if (!out || cap < 0) return fail(REWL_EINVAL, "bad output buffer");
+    st = sync_check(ctx);
+    if (st) return st;
+    const WalkerDesc &wd = ctx->wdesc[gw];
+    const int32_t nb = wd.hi - wd.lo;
+    const int32_t n = std::min(nb, cap);
+    HIP_TRY(hipMemcpy(out, (unsigned char *)ctx->buf[buf] + esz * (size_t)wd.bin_off, esz * (size_t)n,
+                      hipMemcpyDeviceToHost));
+    if (n_out) *n_out = n;
+    return REWL_OK;
+}
+
+rewl_status rewl_read_lng(rewl_ctx *ctx, int32_t inst, int32_t walker, double *out, int32_t cap, int32_t *n_out)
+{
+    return read_bins(ctx, inst, walker, REWL_BUF_LNG, sizeof(double), out, cap, n_out);
+}
+
+rewl_status rewl_read_hist(rewl_ctx *ctx, int32_t inst, int32_t walker, uint32_t *out, int32_t cap, int32_t *n_out)
+{
+    return read_bins(ctx, inst, walker, REWL_BUF_HIST, sizeof(uint32_t), out, cap, n_out);
+}
+
+rewl_status rewl_read_visited(rewl_ctx *ctx, int32_t inst, int32_t walker, uint8_t *out, int32_t cap, int32_t *n_out)
+{
+    return read_bins(ctx, inst, walker, REWL_BUF_VISITED, 1, out, cap, n_out);
+}
+
+rewl_status rewl_read_walker_state(rewl_ctx *ctx, int32_t inst, int32_t walker, rewl_walker_state *out)
+{
+    int gw;
+    rewl_status st = check_walker(ctx, inst, walker, &gw);
+    if (st) return st;
+    if (!out) return fail(REWL_EINVAL, "null output");
+    st = sync_check(ctx);
+    if (st) return st;
+    WalkerState ws;
+    HIP_TRY(hipMemcpy(&ws, (WalkerState *)ctx->buf[REWL_BUF_STATE] + gw, sizeof ws, hipMemcpyDeviceToHost));
+    out->E = ws.E;
+    out->lnf = ws.lnf;
+    out->max_drift = ws.max_drift;
+    out->bin = ws.bin;
+    out->config = ws.cfg;
+    out->iteration = ws.iter;
+    out->done = ws.done;
+    out->n_visited = ws.nvis;
+    out->window = ctx->wdesc[gw].win;
+    out->attempts = ws.attempts;
+    out->accepts = ws.accepts;
+    out->rejected_outside = ws.oow;
+    if (ws.status == REWL_ENUMERIC) return fail(REWL_ENUMERIC, "non-finite energy or ln g");
+    return REWL_OK;
+}
+
+rewl_status rewl_read_config(rewl_ctx *ctx, int32_t inst, int32_t config, double *out, int64_t cap)
+{
+    if (!ctx || !out) return fail(REWL_EINVAL, "null argument");
+    if (ctx->stage < 3) return fail(REWL_ESTATE, "walkers not initialised");
+    if (inst < 0 || inst >= (int32_t)ctx->inst.size()) return fail(REWL_EINVAL, "bad instance index");
+    const InstDesc &d = ctx->idesc[inst];
+    if (config < 0 || config >= d.n_walkers) return fail(REWL_EINVAL, "bad configuration index");
+    if (cap < 3 * (int64_t)d.N) return fail(REWL_EINVAL, "output too small");
+    rewl_status st = sync_check(ctx);
+    if (st) return st;
+    const size_t sb = spin_bytes(ctx->mode);
+    std::vector<unsigned char> tmp(sb * (size_t)d.N);
+    HIP_TRY(hipMemcpy(tmp.data(), (unsigned char *)ctx->buf[REWL_BUF_SPINS] + sb * (size_t)(d.cfg_off + (int64_t)config * d.N),
+                      tmp.size(), hipMemcpyDeviceToHost));
+    for (int i = 0; i < d.N; ++i)
+        for (int k = 0; k < 3; ++k)
+            out[3 * (size_t)i + k] = sb == 16 ? (double)((const float *)tmp.data())[4 * (size_t)i + k]
+                                              : ((const double *)tmp.data())[4 * (size_t)i + k];
+    return REWL_OK;
+}
+
+rewl_status rewl_read_window(rewl_ctx *ctx, int32_t inst, int32_t win, int32_t *lo_bin, int32_t *hi_bin)
+{
+    if (!ctx || !lo_bin || !hi_bin) return fail(REWL_EINVAL, "null argument");
+    if (ctx->stage < 1) return fail(REWL_ESTATE, "call rewl_query_sizes first");
+    if (inst < 0 || inst >= (int32_t)ctx->inst.size()) return fail(REWL_EINVAL, "bad instance index");
+    const InstanceCfg &q = ctx->inst[inst];
+    if (win < 0 || win >= q.h) return fail(REWL_EINVAL, "bad window index");
+    *lo_bin = q.lo[win];
+    *hi_bin = q.hi[win];
+    return REWL_OK;
+}
+
+rewl_status rewl_read_exchange_stats(rewl_ctx *ctx, int32_t inst, uint64_t *attempts, uint64_t *accepts, int32_t cap)
+{
+    if (!ctx || !attempts || !accepts) return fail(REWL_EINVAL, "null argument");
+    if (ctx->stage < 3) return fail(REWL_ESTATE, "walkers not initialised");
+    if (inst < 0 || inst >= (int32_t)ctx->inst.size()) return fail(REWL_EINVAL, "bad instance index");
+    rewl_status st = sync_check(ctx);
+    if (st) return st;
+    const InstDesc &d = ctx->idesc[inst];
+    const int n = std::min(cap, std::max(d.h - 1, 0));
+    unsigned char *Cb = (unsigned char *)ctx->buf[REWL_BUF_CONTROL];
+    if (n > 0) {
+        HIP_TRY(hipMemcpy(attempts, Cb + ctx->off_xatt + 8 * (size_t)d.xstat_off, 8 * (size_t)n, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(accepts, Cb + ctx->off_xacc + 8 * (size_t)d.xstat_off, 8 * (size_t)n, hipMemcpyDeviceToHost));
+    }
+    return REWL_OK;
+}
+
+rewl_status rewl_read_step(rewl_ctx *ctx, int64_t *step_out)
+{
+    if (!ctx || !step_out) return fail(REWL_EINVAL, "null argument");
+    *step_out = ctx->t;
+    return REWL_OK;
+}
+
+rewl_status rewl_total_attempts(rewl_ctx *ctx, uint64_t *attempts, uint64_t *accepts)
+{
+    if (!ctx || !attempts || !accepts) return fail(REWL_EINVAL, "null argument");
+    if (ctx->stage < 3) return fail(REWL_ESTATE, "walkers not initialised");
+    rewl_status st = sync_check(ctx);
+    if (st) return st;
+    std::vector<WalkerState> ws(ctx->n_walkers);
+    HIP_TRY(hipMemcpy(ws.data(), ctx->buf[REWL_BUF_STATE], sizeof(WalkerState) * ws.size(), hipMemcpyDeviceToHost));
+    uint64_t at = 0, ac = 0;
+    for (auto &w : ws) {
+        at += w.attempts;
+        ac += w.accepts;
+    }
+    *attempts = at;
+    *accepts = ac;
+    return REWL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// rewl_internal.h -- layouts shared by the librewl host code and its kernels.
+#pragma once
+
+#include <stdint.h>
+#include <hip/hip_runtime.h>
+#include "../../include/rewl.h"
+
+namespace rewl {
+
+enum Lattice : int32_t { LAT_BCC = 0, LAT_TABLE = 1 };
+
+// Philox stream tags: the fourth counter word of every draw.
+enum Tag : uint32_t {
+    TAG_SITE = 0,          // site choice and acceptance uniform of a trial move
+    TAG_SPHERE = 1,        // proposal direction of a trial move
+    TAG_INIT_SITE = 2,     // drive into the window: site
+    TAG_INIT_SPHERE = 3,   // drive into the window: direction
+    TAG_EXCH = 4,          // replica-exchange acceptance uniform
+    TAG_PERM = 5,          // pairing permutation of an exchange step
+    TAG_INIT_CONFIG = 6    // random initial configuration
+};
+
+// Read-only description of one REWL instance.
+struct InstDesc {
+    int32_t N, L, lattice, z;          // sites, cells per edge, lattice kind, neighbours/site
+    int32_t h, m, B, walker_base;      // windows, walkers/window, global bins, first walker
+    int32_t n_walkers, slot_off, flat_num, flat_den;
+    int32_t xstat_off, nb_max, deg_off, pad1;   // deg_off: first entry in the degree table
+    double Emin, inv_de, lnf_final, lnf_init;
+    int64_t seg_len, resync;
+    int64_t cfg_off;                   // spin element offset of configuration 0
+    int64_t tab_off;                   // element offset in the neighbour table
+    int64_t init_off;                  // double offset of the caller's start spins, -1 = random
+};
+
+// Read-only description of one walker.
+struct WalkerDesc {
+    int32_t inst, win, lo, hi;         // instance, window, window bins [lo, hi)
+    int64_t bin_off;                   // element offset of its window in LNG/HIST/VISITED
+    uint32_t stream;                   // global walker id: second Philox key word
+    int32_t local;                     // index within its instance
+};
+
+// Dynamic per-walker state (device).
+struct WalkerState {
+    double E, lnf, max_drift;
+    int32_t bin, cfg, iter, done, nvis, status;
+    uint64_t attempts, accepts, oow;
+};
+
+// One bcc neighbour slot: cell displacement for a site on sublattice 0 and
+// on sublattice 1, whether the neighbour is on the other sublattice, and
+// the shell's coupling.
+struct BccSlot {
+    int8_t d[2][3];
+    uint8_t flip;
+    uint8_t pad;
+    float Jf;
+    double Jd;
+};
+
+// Per-instance control words (device, CONTROL buffer).
+struct InstControl {
+    int32_t done;
+    int32_t pad;
+};
+
+struct KArgs {
+    void *spins;
+    WalkerState *state;
+    double *lng;
+    uint32_t *hist;
+    uint8_t *vis;
+    const InstDesc *inst;
+    const WalkerDesc *wdesc;
+    const BccSlot *slots;
+    const int32_t *tdeg;
+    const int32_t *tnbr;
+    const double *tJ;
+    const double *init_spins;
+    InstControl *ictl;
+    unsigned long long *xatt;
+    unsigned long long *xacc;
+    rewl_trace_rec *trace;
+    int64_t trace_cap;
+    int64_t t;                 // exchange step counter
+    uint32_t seed;
+    int32_t n_walkers;
+    int32_t n_inst;
+    int32_t walkers_per_block;
+    int32_t lds_spins_bytes;   // bytes of LDS for spins per walker slot
+    int32_t lds_bins;          // window bins per walker slot in LDS
+};
+
+constexpr int kWave = 64;
+
+// Kernel launchers (rewl_kernels.hip).
+int launch_init(const KArgs &a, int mode, hipStream_t s, size_t lds_per_walker);
+int launch_sweep(const KArgs &a, int mode, hipStream_t s, size_t lds_per_walker);
+int launch_exchange(const KArgs &a, hipStream_t s);
+
+}  // namespace rewl

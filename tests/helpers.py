@@ -1,0 +1,47 @@
+"""Shared test helpers: build the oracle or the GPU path from one workload
+description (paper_1411_4212_amd.workloads)."""
+import numpy as np
+
+
+def oracle_from(cfg, threads=4, trace=0, check_energy=False):
+    import oracle
+    lat = cfg["lattice"]
+    if lat[0] == "bcc":
+        o = oracle.Oracle(L=lat[1], J=lat[2])
+    else:
+        o = oracle.Oracle(explicit=(lat[1], lat[2], lat[3], lat[4]))
+    o.set_windows(*cfg["windows"])
+    o.set_schedule(*cfg["schedule"])
+    o.set_threads(threads)
+    if trace:
+        o.set_trace(trace)
+    if check_energy:
+        o.set_check_energy(True)
+    o.init(cfg["seed"])
+    return o
+
+
+def gpu_from(cfgs, mode, trace=0, seed=None):
+    from paper_1411_4212_amd.rewl import Run
+    if isinstance(cfgs, dict):
+        cfgs = [cfgs]
+    r = Run([dict(lattice=c["lattice"], windows=c["windows"], schedule=c["schedule"])
+             for c in cfgs], mode=mode, trace_cap=trace)
+    r.init(cfgs[0]["seed"] if seed is None else seed)
+    return r
+
+
+def joined_lng(read_lng, read_vis, window, h, m):
+    """Combine walkers per window and join windows (oracle analysis)."""
+    from oracle.analysis import combine_walkers, join_windows
+    frags = []
+    for k in range(h):
+        ws = range(k * m, (k + 1) * m)
+        lo, hi = window(k * m)
+        lg, vis = combine_walkers([read_lng(w) for w in ws], [read_vis(w) for w in ws])
+        frags.append((lo, hi, lg, vis))
+    return join_windows(frags)
+
+
+def bits(x):
+    return np.asarray(x, dtype=np.float64).view(np.uint64)

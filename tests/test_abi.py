@@ -1,0 +1,48 @@
+"""The C ABI library loads and exports every symbol include/rewl.h declares
+(CPU only: no compute call)."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "rewl.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:rewl_status|void|const char \*)\s*\*?(rewl_\w+)\s*\(",
+                                 txt, re.M)))
+
+
+def test_library_exports_all_declared_symbols():
+    from paper_1411_4212_amd.build import LIB
+    assert os.path.exists(LIB), "librewl.so not built"
+    lib = ctypes.CDLL(LIB)
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_every_symbol():
+    from paper_1411_4212_amd import rewl
+    assert sorted(rewl.EXPORTED) == _declared()
+    for n in _declared():
+        assert callable(getattr(rewl, n))
+
+
+def test_errors_without_device():
+    """Argument checks and error reporting work before any GPU use."""
+    from paper_1411_4212_amd import rewl
+    import pytest
+    with pytest.raises(rewl.RewlError) as e:
+        rewl.rewl_create(0, 0, 99)
+    assert e.value.code == -1
+    assert "mode" in rewl.rewl_last_error()
+    assert rewl.rewl_poll.__name__ == "rewl_poll"
+
+
+def test_trace_record_layout():
+    from paper_1411_4212_amd import rewl
+    import oracle
+    assert rewl.TRACE_DTYPE.itemsize == 24
+    assert rewl.TRACE_DTYPE == oracle.TRACE_DTYPE
