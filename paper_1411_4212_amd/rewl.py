@@ -13,6 +13,10 @@ import ctypes as C
 import os
 
 import numpy as np
+# torch first: its bundled HIP runtime then satisfies librewl's
+# libamdhip64.so.7 / libhsa-runtime64.so.1 dependencies, so the process holds
+# one HIP runtime and torch's device pointers and streams are valid in ours.
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librewl.so")
