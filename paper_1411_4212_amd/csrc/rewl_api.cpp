@@ -107,6 +107,8 @@ struct rewl_ctx {
     int32_t lds_spins_bytes = 0, lds_bins = 0;
     size_t lds_per_walker = 0;
     int32_t wpb = 1;
+    int32_t fast_q = 0;
+    int32_t all_pow2 = 0;
     uint32_t seed = 0;
     int64_t t = 0;
     rewl_trace_rec *trace = nullptr;
@@ -155,6 +157,8 @@ KArgs make_args(rewl_ctx *c)
     a.walkers_per_block = c->wpb;
     a.lds_spins_bytes = c->lds_spins_bytes;
     a.lds_bins = c->lds_bins;
+    a.fast_q = c->fast_q;
+    a.all_pow2 = c->all_pow2;
     return a;
 }
 
@@ -298,10 +302,26 @@ rewl_status finalize(rewl_ctx *c)
     c->total_spins = cfg_off;
     c->lds_spins_bytes = (int32_t)(((size_t)max_N * spin_bytes(c->mode) + 15) & ~(size_t)15);
     c->lds_bins = (max_nb + 15) & ~15;
-    c->lds_per_walker = (size_t)c->lds_spins_bytes + (size_t)c->lds_bins * 13u;
+    // core region (spins, ln g, H, visited) + the look-ahead batch of the fast kernel
+    c->lds_per_walker = (((size_t)c->lds_spins_bytes + (size_t)c->lds_bins * 13u + 15) & ~(size_t)15) + 64 * 48;
     if (c->lds_per_walker > 160 * 1024)
         return fail(REWL_EUNSUPPORTED, "configuration plus window does not fit in 160 KB of LDS");
     c->wpb = 1;
+    // the fast kernel covers bcc lattices with L a power of two or L <= 64
+    c->fast_q = 0;
+    if (c->mode != REWL_MODE_FP64_DET) {
+        bool ok = true, p2 = true;
+        int zmax = 0;
+        for (size_t ii = 0; ii < c->inst.size(); ++ii) {
+            const InstanceCfg &q = c->inst[ii];
+            const bool pow2 = (q.L & (q.L - 1)) == 0;
+            ok &= q.lattice == LAT_BCC && q.L >= 4 && (pow2 || q.L <= 64);
+            p2 &= pow2;
+            zmax = std::max(zmax, c->idesc[ii].z);
+        }
+        if (ok) c->fast_q = zmax <= 16 ? 1 : (zmax <= 64 ? 4 : 8);
+        c->all_pow2 = p2 ? 1 : 0;
+    }
 
     size_t o = 0;
     c->off_inst = o;

@@ -90,6 +90,8 @@ struct KArgs {
     int32_t walkers_per_block;
     int32_t lds_spins_bytes;   // bytes of LDS for spins per walker slot
     int32_t lds_bins;          // window bins per walker slot in LDS
+    int32_t fast_q;            // >0: fast sweep kernel with this many neighbour slots per lane
+    int32_t all_pow2;          // every instance has L a power of two
 };
 
 constexpr int kWave = 64;

@@ -50,10 +50,18 @@ struct WalkerLds {
     uint8_t *vis;
 };
 
+// Per-walker LDS: spins | ln g (FP64) | H (u32) | visited (u8) | look-ahead
+// batch of 64 trial moves (fast kernel).
+constexpr size_t kBatchBytes = 64 * (32 + 4 + 4 + 8);
+
+__device__ __forceinline__ size_t lds_core_bytes(const KArgs &a)
+{
+    return ((size_t)a.lds_spins_bytes + (size_t)a.lds_bins * 13u + 15) & ~(size_t)15;
+}
+
 __device__ __forceinline__ WalkerLds carve_lds(unsigned char *base, const KArgs &a, int slot)
 {
-    const size_t per = (size_t)a.lds_spins_bytes + (size_t)a.lds_bins * 13u;
-    const size_t per_al = (per + 15) & ~(size_t)15;
+    const size_t per_al = lds_core_bytes(a) + kBatchBytes;
     unsigned char *p = base + per_al * (size_t)slot;
     WalkerLds w;
     w.spins = p;
@@ -274,7 +282,7 @@ __global__ void __launch_bounds__(256) init_kernel(KArgs a)
     using T = typename Spin<MODE>::T;
     using V = typename Spin<MODE>::V;
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int wave = threadIdx.x / kWave;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = __lane_id();
     const int w = blockIdx.x * a.walkers_per_block + wave;
     if (w >= a.n_walkers) return;
@@ -363,7 +371,7 @@ __global__ void __launch_bounds__(256) sweep_kernel(KArgs a)
     using T = typename Spin<MODE>::T;
     using V = typename Spin<MODE>::V;
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int wave = threadIdx.x / kWave;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = __lane_id();
     const int w = blockIdx.x * a.walkers_per_block + wave;
     if (w >= a.n_walkers) return;
@@ -609,6 +617,380 @@ __global__ void __launch_bounds__(64) exchange_kernel(KArgs a)
     if (tid == 0 && all_done) a.ictl[ii].done = 1;
 }
 
+
+// ------------------------------------------------------------------ fast sweep
+// The same segment as sweep_kernel for the FP32_DE and FP64 modes on bcc
+// lattices, organised for one wavefront:
+//  * every 64 trial moves, lane j draws the random numbers of move n0 + j
+//    (site, acceptance uniform as ln u, proposal) into an LDS batch: these do
+//    not depend on the walk;
+//  * the wavefront then treats four moves at a time: lane group g (16 lanes)
+//    gathers the neighbours of move g's site (slots r, r+16, ...), the groups
+//    sum their partial fields with DPP row operations and compute dE of their
+//    move from the current spins;
+//  * the moves are then decided one after the other; an accepted move that
+//    changes a spin of a later move's neighbourhood (or its own site) marks
+//    the pass stale and the remaining moves' fields are recomputed from the
+//    updated spins, so every decision uses exactly the current configuration;
+//  * u < g(E_A)/g(E_B) is tested as ln u < ln g(E_A) - ln g(E_B);
+//  * unvisited bins hold NaN in the LDS copy of ln g, so the move loop reads
+//    one LDS word for the proposed bin and writes no visited flags.
+// Neighbour indices: for L a power of two the site index is the bit field
+// (x | y << k | z << 2k | s << 3k) and a neighbour is a field-wise addition
+// modulo L (carry-free SWAR add); otherwise coordinates are packed in 8-bit
+// fields and wrapped by a packed compare-subtract.
+template <int CTRL>
+__device__ __forceinline__ float rowsum_step_f(float v) { return v + dpp_f<CTRL>(v); }
+template <int CTRL>
+__device__ __forceinline__ double rowsum_step_d(double v) { return v + dpp_d<CTRL>(v); }
+
+template <typename T>
+__device__ __forceinline__ T row_sum16(T v)
+{
+    if constexpr (sizeof(T) == 4) {
+        v = rowsum_step_f<0xB1>(v);
+        v = rowsum_step_f<0x4E>(v);
+        v = rowsum_step_f<0x124>(v);
+        v = rowsum_step_f<0x128>(v);
+    } else {
+        v = rowsum_step_d<0xB1>(v);
+        v = rowsum_step_d<0x4E>(v);
+        v = rowsum_step_d<0x124>(v);
+        v = rowsum_step_d<0x128>(v);
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T readlane_t(T v, int l)
+{
+    if constexpr (sizeof(T) == 4) return readlane_f(v, l);
+    else return readlane_d(v, l);
+}
+
+__device__ __forceinline__ double uniform_d(double v)
+{
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+template <typename T>
+__device__ __forceinline__ T fma_t(T a, T b, T c)
+{
+    if constexpr (sizeof(T) == 4) return __builtin_fmaf(a, b, c);
+    else return __builtin_fma(a, b, c);
+}
+
+struct FastLat {
+    int L, k, L3, pow2;
+    uint32_t M, Hm;          // SWAR masks: field bits below the top bit / top bits
+};
+
+template <int MODE, int Q, bool POW2>
+__global__ void __launch_bounds__(256) sweep_fast_kernel(KArgs a)
+{
+    using T = typename Spin<MODE>::T;
+    using V = typename Spin<MODE>::V;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = __lane_id();
+    const int w = blockIdx.x * a.walkers_per_block + wave;
+    if (w >= a.n_walkers) return;
+    const WalkerDesc wd = a.wdesc[w];
+    if (a.ictl[wd.inst].done) return;
+    const InstDesc I = a.inst[wd.inst];
+    WalkerState st = a.state[w];
+    if (st.status != 0) return;
+    WalkerLds Ld = carve_lds(lds_raw, a, wave);
+    V *S = (V *)Ld.spins;
+    unsigned char *bbase = (unsigned char *)lds_raw +
+                           (lds_core_bytes(a) + kBatchBytes) * (size_t)wave + lds_core_bytes(a);
+    V *b_prop = (V *)bbase;
+    int32_t *b_site = (int32_t *)(bbase + 64 * sizeof(V));
+    int32_t *b_code = b_site + 64;
+    double *b_lnu = (double *)(b_code + 64);
+
+    const int N = I.N;
+    const int nb = wd.hi - wd.lo;
+    const int ilo = wd.lo;
+    V *G = (V *)a.spins + I.cfg_off + (int64_t)st.cfg * N;
+    copy_spins<MODE>(S, G, N);
+    double *glng = a.lng + wd.bin_off;
+    uint32_t *gH = a.hist + wd.bin_off;
+    uint8_t *gvis = a.vis + wd.bin_off;
+    const double qnan = __longlong_as_double(0x7ff8000000000000ll);
+    for (int j = lane; j < nb; j += kWave) {
+        Ld.lng[j] = (gvis[j] || j == st.bin - ilo) ? glng[j] : qnan;
+        Ld.H[j] = gH[j];
+    }
+
+    // lattice constants and this lane's neighbour slots
+    FastLat fl;
+    fl.L = I.L;
+    fl.pow2 = POW2 ? 1 : ((I.L & (I.L - 1)) == 0);
+    fl.k = 31 - __clz(I.L);
+    fl.L3 = I.L * I.L * I.L;
+    {
+        uint32_t one = 1u | (1u << fl.k) | (1u << (2 * fl.k));
+        uint32_t full = (uint32_t)fl.L3 - 1u;
+        fl.Hm = (one << (fl.k - 1)) & full;
+        fl.M = full & ~fl.Hm;
+    }
+    const int grp = lane >> 4, r = lane & 15;
+    uint32_t offM[2][Q], offH[2][Q], flipb[Q];
+    T Jq[Q];
+    {
+        const BccSlot *slots = a.slots + I.slot_off;
+        for (int q = 0; q < Q; ++q) {
+            const int k = q * 16 + r;
+            BccSlot sl{};
+            if (k < I.z) sl = slots[k];
+            Jq[q] = (k < I.z) ? ((MODE == M_F32) ? (T)sl.Jf : (T)sl.Jd) : (T)0;
+            flipb[q] = sl.flip;
+            for (int sb = 0; sb < 2; ++sb) {
+                const uint32_t ox = (uint32_t)((sl.d[sb][0] + fl.L) % fl.L);
+                const uint32_t oy = (uint32_t)((sl.d[sb][1] + fl.L) % fl.L);
+                const uint32_t oz = (uint32_t)((sl.d[sb][2] + fl.L) % fl.L);
+                if (fl.pow2) {
+                    const uint32_t off = ox | (oy << fl.k) | (oz << (2 * fl.k));
+                    offM[sb][q] = off & fl.M;
+                    offH[sb][q] = off & fl.Hm;
+                } else {
+                    offM[sb][q] = ox | (oy << 8) | (oz << 16);
+                    offH[sb][q] = 0;
+                }
+            }
+        }
+    }
+    wave_sync();
+
+    const double inv = I.inv_de;
+    const double emin_inv = I.Emin * inv;
+    const double lo = (double)wd.lo, hi = (double)wd.hi;
+    double E = st.E;
+    int bin = st.bin;
+    const double lnf = st.lnf;
+    const bool frozen = st.done != 0;
+    const bool discovering = (st.iter == 0) && !frozen;
+    double cur = uniform_d(Ld.lng[bin - ilo]);
+    const uint64_t n_begin = st.attempts;
+    const uint64_t n_end = n_begin + (uint64_t)I.seg_len;
+    uint64_t acc_count = 0, oow = 0;
+    rewl_trace_rec *trace = a.trace ? a.trace + (int64_t)w * a.trace_cap : nullptr;
+    const uint32_t wrapC = 0x00808080u - 0x00010101u * (uint32_t)fl.L;   // 128 - L per 8-bit field
+
+    int nidx[Q];
+    T dEv = 0;
+    // gather + field + dE of the move held by this lane's group (batch slot p + grp)
+    auto fields = [&](int p) {
+        const int e = p + grp;
+        const int code = b_code[e];
+        const int site = b_site[e];
+        // the site's own spin and the proposal are read with the gather
+        const V si = S[site];
+        const V pr = b_prop[e];
+        T px = 0, py = 0, pz = 0;
+        const int sb = (POW2 || fl.pow2) ? (code >> (3 * fl.k)) : (code >> 24);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            int j;
+            const int t = sb ^ (int)flipb[q];
+            if (POW2 || fl.pow2) {
+                const uint32_t aa = (uint32_t)code & (uint32_t)(fl.L3 - 1);
+                const uint32_t om = sb ? offM[1][q] : offM[0][q];
+                const uint32_t oh = sb ? offH[1][q] : offH[0][q];
+                j = (int)((((aa & fl.M) + om) ^ (aa & fl.Hm) ^ oh) | ((uint32_t)t << (3 * fl.k)));
+            } else {
+                uint32_t sum = ((uint32_t)code & 0x00FFFFFFu) + (sb ? offM[1][q] : offM[0][q]);
+                const uint32_t gt = ((sum + wrapC) >> 7) & 0x00010101u;
+                sum -= gt * (uint32_t)fl.L;
+                j = (int)(sum & 0xFF) + fl.L * ((int)((sum >> 8) & 0xFF) + fl.L * ((int)(sum >> 16) + fl.L * t));
+            }
+            nidx[q] = j;
+            const V s = S[j];
+            px = fma_t<T>(Jq[q], s.x, px);
+            py = fma_t<T>(Jq[q], s.y, py);
+            pz = fma_t<T>(Jq[q], s.z, pz);
+        }
+        const T hx = row_sum16(px), hy = row_sum16(py), hz = row_sum16(pz);
+        if constexpr (MODE == M_F32) {
+            dEv = -__builtin_fmaf(pr.z - si.z, hz, __builtin_fmaf(pr.y - si.y, hy, (pr.x - si.x) * hx));
+        } else {
+            dEv = -(((pr.x - si.x) * hx + (pr.y - si.y) * hy) + (pr.z - si.z) * hz);
+        }
+    };
+
+    int my_site = 0;
+    double my_lnu = 0.0;
+    for (uint64_t n0 = n_begin; n0 < n_end; n0 += 64) {
+        // draw the random numbers of moves n0 .. n0+63, one per lane
+        {
+            const uint64_t nn = n0 + (uint64_t)lane;
+            const U4 rr = draw(a.seed, wd.stream, nn, 0u, TAG_SITE);
+            const int site = pick_site(rr.x, N);
+            const double u = u53(rr.y, rr.z);
+            T px, py, pz;
+            propose<MODE>(a.seed, wd.stream, nn, TAG_SPHERE, px, py, pz);
+            int code = site;
+            if (!fl.pow2) {
+                int x, y, zc;
+                int qv = divmod_small(site, fl.L, 1.0f / (float)fl.L, x);
+                qv = divmod_small(qv, fl.L, 1.0f / (float)fl.L, y);
+                const int sb = divmod_small(qv, fl.L, 1.0f / (float)fl.L, zc);
+                code = x | (y << 8) | (zc << 16) | (sb << 24);
+            }
+            V pv;
+            pv.x = px;
+            pv.y = py;
+            pv.z = pz;
+            pv.w = (T)0;
+            b_prop[lane] = pv;
+            b_site[lane] = site;
+            b_code[lane] = code;
+            my_site = site;
+            my_lnu = log(u);
+        }
+        wave_sync();
+        const int nvalid = (int)((n_end - n0) < 64 ? (n_end - n0) : 64);
+        for (int p = 0; p < nvalid; p += 4) {
+            fields(p);
+            bool stale = false;
+            const int gmax = (nvalid - p) < 4 ? (nvalid - p) : 4;
+            for (int g = 0; g < gmax; ++g) {
+                if (stale) {
+                    fields(p);
+                    stale = false;
+                }
+                const uint64_t n = n0 + (uint64_t)(p + g);
+                const double dE = (double)readlane_t<T>(dEv, 16 * g);
+                const int site = __builtin_amdgcn_readlane(my_site, p + g);
+                const double lnu = readlane_d(my_lnu, p + g);
+                const double Eb = E + dE;
+                const double xb = __builtin_fma(Eb, inv, -emin_inv);
+                bool accept = false, outside = true;
+                int bb = 0;
+                double lnb = 0.0;
+                if (xb >= lo && xb < hi) {
+                    bb = (int)floor(xb);
+                    lnb = uniform_d(Ld.lng[bb - ilo]);
+                    outside = false;
+                    if (__builtin_isnan(lnb)) {
+                        if (discovering) {
+                            lnb = cur;
+                            Ld.lng[bb - ilo] = cur;
+                            for (int j = lane; j < nb; j += kWave) Ld.H[j] = 0u;
+                        } else {
+                            outside = true;
+                        }
+                    }
+                    if (!outside) {
+                        const double lr = cur - lnb;
+                        accept = (lr >= 0.0) || (lnu < lr);
+                    }
+                }
+                oow += outside ? 1u : 0u;
+                if (accept) {
+                    if (lane == 16 * g) S[site] = b_prop[p + g];
+                    E = Eb;
+                    bin = bb;
+                    cur = lnb;
+                    ++acc_count;
+                    // later moves of this pass whose neighbourhood or site changed
+                    bool hit = (grp > g) && (b_site[p + grp] == site);
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) hit |= (grp > g) && (nidx[q] == site);
+                    stale = __builtin_amdgcn_ballot_w64(hit) != 0ull;
+                }
+                const int jb = bin - ilo;
+                if (!frozen) {
+                    cur = cur + lnf;
+                    Ld.lng[jb] = cur;
+                    Ld.H[jb] = Ld.H[jb] + 1u;
+                }
+                if (trace && n < (uint64_t)a.trace_cap && lane == 0) {
+                    rewl_trace_rec rec;
+                    rec.site = (uint32_t)site;
+                    rec.flags = (accept ? 1u : 0u) | (outside ? 2u : 0u);
+                    rec.E = E;
+                    rec.bin = bin;
+                    rec.attempt_lo = (uint32_t)n;
+                    trace[n] = rec;
+                }
+            }
+        }
+        wave_sync();
+    }
+    const uint64_t n = n_end;
+
+    // resync when due (lane-parallel FP64 energy)
+    LatCtx<MODE> c;
+    load_latctx<MODE>(c, I, a, lane);
+    if (I.resync > 0 && (n / (uint64_t)I.resync) != (n_begin / (uint64_t)I.resync)) {
+        const double ef = full_energy<MODE>(c, S);
+        const double d = fabs(ef - E);
+        if (d > st.max_drift) st.max_drift = d;
+        E = ef;
+        const double x = (ef - I.Emin) * inv;
+        bin = x < lo ? wd.lo : (x >= hi ? wd.hi - 1 : (int)floor(x));
+    }
+
+    // flatness over visited bins, then the ln f update
+    int nvis = 0;
+    unsigned long long sumH = 0;
+    uint32_t minH = 0xFFFFFFFFu;
+    for (int j = lane; j < nb; j += kWave) {
+        if (!__builtin_isnan(Ld.lng[j])) {
+            nvis += 1;
+            sumH += Ld.H[j];
+            minH = Ld.H[j] < minH ? Ld.H[j] : minH;
+        }
+    }
+    nvis = wave_sum_i(nvis);
+    sumH = wave_sum_u64(sumH);
+    minH = wave_min_u32(minH);
+    if (!frozen) {
+        bool flat = false;
+        if (nvis > st.nvis) {
+            flat = false;
+        } else if (nvis > 0 && sumH > 0) {
+            flat = (unsigned long long)I.flat_den * (unsigned long long)minH * (unsigned long long)nvis >=
+                   (unsigned long long)I.flat_num * sumH;
+        }
+        st.nvis = nvis;
+        if (flat) {
+            if (st.lnf <= I.lnf_final) {
+                st.done = 1;
+            } else {
+                st.lnf = st.lnf * 0.5;
+                st.iter += 1;
+                for (int j = lane; j < nb; j += kWave) Ld.H[j] = 0u;
+            }
+        }
+    } else {
+        st.nvis = nvis;
+    }
+    wave_sync();
+
+    copy_spins<MODE>(G, S, N);
+    for (int j = lane; j < nb; j += kWave) {
+        const double v = Ld.lng[j];
+        const bool vis = !__builtin_isnan(v);
+        glng[j] = vis ? v : 0.0;
+        gH[j] = Ld.H[j];
+        gvis[j] = vis ? 1 : 0;
+    }
+    if (lane == 0) {
+        st.E = E;
+        st.bin = bin;
+        st.attempts = n;
+        st.accepts += acc_count;
+        st.oow += oow;
+        if (!isfinite(E) || !isfinite(cur)) st.status = REWL_ENUMERIC;
+        a.state[w] = st;
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 static size_t lds_bytes(const KArgs &a, size_t per_walker)
 {
@@ -634,6 +1016,24 @@ int launch_sweep(const KArgs &a, int mode, hipStream_t s, size_t per_walker)
     const int wpb = a.walkers_per_block;
     const dim3 grid((a.n_walkers + wpb - 1) / wpb), block(kWave * wpb);
     const size_t lds = lds_bytes(a, per_walker);
+    if (a.fast_q > 0 && mode != M_DET) {
+#define REWL_FAST(M, Qv, P2) hipLaunchKernelGGL((sweep_fast_kernel<M, Qv, P2>), grid, block, lds, s, a)
+#define REWL_FAST_Q(M, P2)                          \
+    switch (a.fast_q) {                             \
+    case 1: REWL_FAST(M, 1, P2); break;             \
+    case 4: REWL_FAST(M, 4, P2); break;             \
+    case 8: REWL_FAST(M, 8, P2); break;             \
+    default: return REWL_EINVAL;                    \
+    }
+        if (mode == M_F32) {
+            if (a.all_pow2) { REWL_FAST_Q(M_F32, true) } else { REWL_FAST_Q(M_F32, false) }
+        } else {
+            if (a.all_pow2) { REWL_FAST_Q(M_F64, true) } else { REWL_FAST_Q(M_F64, false) }
+        }
+#undef REWL_FAST_Q
+#undef REWL_FAST
+        return hipGetLastError() == hipSuccess ? REWL_OK : REWL_EDEVICE;
+    }
     switch (mode) {
     case M_DET: hipLaunchKernelGGL(sweep_kernel<M_DET>, grid, block, lds, s, a); break;
     case M_F64: hipLaunchKernelGGL(sweep_kernel<M_F64>, grid, block, lds, s, a); break;

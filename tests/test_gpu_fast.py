@@ -1,0 +1,81 @@
+"""Fast GPU modes (FP32_DE and FP64 with the look-ahead kernel): invariants
+that hold for any trajectory, checked through the C ABI."""
+import sys
+
+import numpy as np
+import pytest
+
+from helpers import gpu_from
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("mode", ["fp32_de", "fp64"])
+@pytest.mark.parametrize("which", ["c1", "c2"])
+def test_fast_invariants(mode, which):
+    """After 12 segments: every walker made exactly 12 x 1e4 moves, its
+    running energy equals the full energy of the configuration it holds
+    (FP64 oracle energy function) up to the mode's rounding drift, its bin is
+    the bin of that energy and lies in its window, the configurations are a
+    permutation, ln f = 2^-iteration, and visited bins carry H or ln g."""
+    import oracle
+    from paper_1411_4212_amd import workloads
+    cfg = getattr(workloads, which)()
+    _say(which, mode)
+    g = gpu_from(cfg, mode)
+    g.run(12)
+    lat = cfg["lattice"]
+    o = oracle.Oracle(L=lat[1], J=lat[2])
+    Emin, Emax, B = cfg["windows"][:3]
+    inv = B / (Emax - Emin)
+    W = g.n_walkers
+    cfgs = []
+    tol = 2e-3 if mode == "fp32_de" else 1e-8
+    for w in range(W):
+        st = g.walker(0, w)
+        assert st["attempts"] == 12 * cfg["schedule"][4]
+        assert 0 < st["accepts"] < st["attempts"]
+        assert st["lnf"] == 2.0 ** -st["iteration"]
+        S = g.config(0, st["config"])
+        assert np.allclose(np.linalg.norm(S, axis=1), 1.0, atol=1e-6 if mode == "fp32_de" else 1e-14)
+        Ef = o.energy(S)
+        assert abs(Ef - st["E"]) <= tol * (1 + abs(Ef)) ** 0.5 * 10, (w, Ef, st["E"])
+        lo, hi = g.window(0, w)
+        assert lo <= st["bin"] < hi
+        assert st["bin"] == int(np.floor((st["E"] - Emin) * inv)) or abs(
+            (st["E"] - Emin) * inv - round((st["E"] - Emin) * inv)) < 1e-9
+        vis = g.visited(0, w)
+        assert vis[st["bin"] - lo]
+        assert vis.sum() == st["n_visited"]
+        cfgs.append(st["config"])
+    assert sorted(cfgs) == list(range(W))
+    att, acc = g.exchange_stats(0)
+    assert att.sum() > 0
+
+
+def test_fast_matches_oracle_early_trajectory():
+    """FP64 fast mode makes the same decisions as the oracle while rounding
+    differences stay below the bin and acceptance resolution: the first 200
+    moves of every C1 walker (same Philox streams) agree in site, accept bit
+    and bin with the oracle's trajectory."""
+    from helpers import oracle_from
+    from paper_1411_4212_amd import workloads
+    cfg = workloads.c1()
+    o = oracle_from(cfg, trace=200)
+    o.run(1)
+    g = gpu_from(cfg, "fp64", trace=200)
+    g.run(1)
+    agree = 0
+    for w in range(4):
+        to, tg = o.trace(w), g.trace(w)
+        assert np.array_equal(to["site"], tg["site"])
+        same = (to["flags"] == tg["flags"]) & (to["bin"] == tg["bin"])
+        k = int(np.argmin(same)) if not same.all() else len(same)
+        agree += k
+        assert k >= 150, (w, k)
+    assert agree >= 700
