@@ -163,6 +163,21 @@ rewl_status rewl_set_schedule(rewl_ctx *ctx, int32_t inst, int32_t flat_num, int
                               double lnf_init, double lnf_final, int64_t exchange_interval,
                               int64_t resync_interval);
 
+/* Launch shape of the trial-move kernel (after rewl_query_sizes).
+ * walkers_per_block: 1..4 walkers (one wavefront each) per workgroup
+ * (several workgroups share a compute unit when LDS allows).
+ * residency: 0 = automatic (configurations in LDS when a configuration, its
+ * window and the look-ahead batch fit in 160 KB, else read and written in
+ * place in HBM), 1 = LDS, 2 = HBM (FP32_DE / FP64 modes on bcc lattices).
+ * Fails with REWL_EUNSUPPORTED when the shape does not fit, leaving the
+ * previous shape in place. */
+rewl_status rewl_set_launch(rewl_ctx *ctx, int32_t walkers_per_block, int32_t residency);
+
+/* The launch shape in use: walkers per block, 1 if configurations are staged
+ * in LDS, and LDS bytes per workgroup. */
+rewl_status rewl_get_launch(rewl_ctx *ctx, int32_t *walkers_per_block, int32_t *spins_in_lds,
+                            int64_t *lds_bytes_per_block);
+
 /* Byte sizes of the REWL_NBUF device buffers the caller must provide. */
 rewl_status rewl_query_sizes(rewl_ctx *ctx, size_t *bytes_out /* [REWL_NBUF] */);
 

@@ -106,6 +106,10 @@ struct rewl_ctx {
     int64_t total_bins = 0, total_spins = 0;
     int32_t lds_spins_bytes = 0, lds_bins = 0;
     size_t lds_per_walker = 0;
+    int32_t max_N = 0;
+    int32_t residency_req = 0;   // 0 auto, 1 LDS, 2 HBM
+    int32_t wpb_req = 1;
+    int32_t spins_in_lds = 1;
     int32_t wpb = 1;
     int32_t fast_q = 0;
     int32_t all_pow2 = 0;
@@ -155,11 +159,37 @@ KArgs make_args(rewl_ctx *c)
     a.n_walkers = c->n_walkers;
     a.n_inst = (int32_t)c->inst.size();
     a.walkers_per_block = c->wpb;
-    a.lds_spins_bytes = c->lds_spins_bytes;
+    a.lds_spins_bytes = c->spins_in_lds ? c->lds_spins_bytes : 0;
+    a.spins_in_lds = c->spins_in_lds;
     a.lds_bins = c->lds_bins;
     a.fast_q = c->fast_q;
     a.all_pow2 = c->all_pow2;
     return a;
+}
+
+// Where configurations live during a segment and how many walkers share a
+// workgroup: LDS when the configuration, its window and the look-ahead batch
+// fit in 160 KB, otherwise in place in HBM (fast kernel only).
+rewl_status plan_launch(rewl_ctx *c)
+{
+    const size_t bins = ((size_t)c->lds_bins * 13u + 15) & ~(size_t)15;
+    const size_t batch = 64 * 48;
+    const size_t with_spins = (((size_t)c->lds_spins_bytes + (size_t)c->lds_bins * 13u + 15) & ~(size_t)15) + batch;
+    const size_t without = bins + batch;
+    const size_t cap = 160 * 1024;
+    bool in_lds;
+    if (c->residency_req == 1) in_lds = true;
+    else if (c->residency_req == 2) in_lds = false;
+    else in_lds = with_spins <= cap || c->fast_q == 0;
+    if (!in_lds && c->fast_q == 0)
+        return fail(REWL_EUNSUPPORTED, "spins in HBM need the fast kernel (FP32_DE/FP64 mode, bcc lattice)");
+    const size_t per = in_lds ? with_spins : without;
+    if (per * (size_t)c->wpb_req > cap)
+        return fail(REWL_EUNSUPPORTED, "walkers per block x LDS per walker exceeds 160 KB");
+    c->spins_in_lds = in_lds ? 1 : 0;
+    c->lds_per_walker = per;
+    c->wpb = c->wpb_req;
+    return REWL_OK;
 }
 
 // Build the read-only tables and compute buffer sizes.
@@ -300,13 +330,9 @@ rewl_status finalize(rewl_ctx *c)
     c->n_xstat = xstat;
     c->total_bins = bin_off;
     c->total_spins = cfg_off;
+    c->max_N = max_N;
     c->lds_spins_bytes = (int32_t)(((size_t)max_N * spin_bytes(c->mode) + 15) & ~(size_t)15);
     c->lds_bins = (max_nb + 15) & ~15;
-    // core region (spins, ln g, H, visited) + the look-ahead batch of the fast kernel
-    c->lds_per_walker = (((size_t)c->lds_spins_bytes + (size_t)c->lds_bins * 13u + 15) & ~(size_t)15) + 64 * 48;
-    if (c->lds_per_walker > 160 * 1024)
-        return fail(REWL_EUNSUPPORTED, "configuration plus window does not fit in 160 KB of LDS");
-    c->wpb = 1;
     // the fast kernel covers bcc lattices with L a power of two or L <= 64
     c->fast_q = 0;
     if (c->mode != REWL_MODE_FP64_DET) {
@@ -322,7 +348,10 @@ rewl_status finalize(rewl_ctx *c)
         if (ok) c->fast_q = zmax <= 16 ? 1 : (zmax <= 64 ? 4 : 8);
         c->all_pow2 = p2 ? 1 : 0;
     }
-
+    {
+        rewl_status st = plan_launch(c);
+        if (st) return st;
+    }
     size_t o = 0;
     c->off_inst = o;
     o = align256(o + sizeof(InstDesc) * c->idesc.size());
@@ -596,6 +625,36 @@ rewl_status rewl_run(rewl_ctx *ctx, int64_t n_segments)
         if (rc) return fail(rc, "exchange kernel launch failed");
         ctx->t += 1;
     }
+    return REWL_OK;
+}
+
+rewl_status rewl_set_launch(rewl_ctx *ctx, int32_t walkers_per_block, int32_t residency)
+{
+    if (!ctx) return fail(REWL_EINVAL, "null context");
+    if (ctx->stage < 1) return fail(REWL_ESTATE, "call rewl_query_sizes first");
+    if (walkers_per_block < 1 || walkers_per_block > 4) return fail(REWL_EINVAL, "walkers per block must be 1..4");
+    if (residency < 0 || residency > 2) return fail(REWL_EINVAL, "residency must be 0 (auto), 1 (LDS) or 2 (HBM)");
+    const int32_t old_w = ctx->wpb_req, old_r = ctx->residency_req;
+    ctx->wpb_req = walkers_per_block;
+    ctx->residency_req = residency;
+    rewl_status st = plan_launch(ctx);
+    if (st) {
+        ctx->wpb_req = old_w;
+        ctx->residency_req = old_r;
+        plan_launch(ctx);
+        return st;
+    }
+    return REWL_OK;
+}
+
+rewl_status rewl_get_launch(rewl_ctx *ctx, int32_t *walkers_per_block, int32_t *spins_in_lds,
+                            int64_t *lds_bytes_per_block)
+{
+    if (!ctx || !walkers_per_block || !spins_in_lds || !lds_bytes_per_block) return fail(REWL_EINVAL, "null argument");
+    if (ctx->stage < 1) return fail(REWL_ESTATE, "call rewl_query_sizes first");
+    *walkers_per_block = ctx->wpb;
+    *spins_in_lds = ctx->spins_in_lds;
+    *lds_bytes_per_block = (int64_t)(((ctx->lds_per_walker + 15) & ~(size_t)15) * (size_t)ctx->wpb);
     return REWL_OK;
 }
 

@@ -92,6 +92,8 @@ struct KArgs {
     int32_t lds_bins;          // window bins per walker slot in LDS
     int32_t fast_q;            // >0: fast sweep kernel with this many neighbour slots per lane
     int32_t all_pow2;          // every instance has L a power of two
+    int32_t spins_in_lds;      // 1: configurations staged in LDS; 0: read in place from HBM
+    int32_t pad2;
 };
 
 constexpr int kWave = 64;

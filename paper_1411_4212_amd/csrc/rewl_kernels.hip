@@ -276,7 +276,7 @@ __device__ __forceinline__ void copy_spins(typename Spin<MODE>::V *dst, const ty
 // ------------------------------------------------------------------ init
 // Start configuration, its energy, and the drive into the window: moves are
 // accepted when the new energy lies in the window or strictly closer to it.
-template <int MODE>
+template <int MODE, bool LDS_SPINS>
 __global__ void __launch_bounds__(256) init_kernel(KArgs a)
 {
     using T = typename Spin<MODE>::T;
@@ -289,7 +289,8 @@ __global__ void __launch_bounds__(256) init_kernel(KArgs a)
     const WalkerDesc wd = a.wdesc[w];
     const InstDesc I = a.inst[wd.inst];
     WalkerLds L = carve_lds(lds_raw, a, wave);
-    V *S = (V *)L.spins;
+    V *G = (V *)a.spins + I.cfg_off + (int64_t)wd.local * I.N;
+    V *S = LDS_SPINS ? (V *)L.spins : G;
     LatCtx<MODE> c;
     load_latctx<MODE>(c, I, a, lane);
 
@@ -344,8 +345,7 @@ __global__ void __launch_bounds__(256) init_kernel(KArgs a)
         }
     }
     wave_sync();
-    V *G = (V *)a.spins + I.cfg_off + (int64_t)wd.local * I.N;
-    copy_spins<MODE>(G, S, I.N);
+    if (LDS_SPINS) copy_spins<MODE>(G, S, I.N);
     if (lane == 0) {
         WalkerState st{};
         st.E = E;
@@ -687,7 +687,7 @@ struct FastLat {
     uint32_t M, Hm;          // SWAR masks: field bits below the top bit / top bits
 };
 
-template <int MODE, int Q, bool POW2>
+template <int MODE, int Q, bool POW2, bool LDS_SPINS>
 __global__ void __launch_bounds__(256) sweep_fast_kernel(KArgs a)
 {
     using T = typename Spin<MODE>::T;
@@ -703,7 +703,6 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(KArgs a)
     WalkerState st = a.state[w];
     if (st.status != 0) return;
     WalkerLds Ld = carve_lds(lds_raw, a, wave);
-    V *S = (V *)Ld.spins;
     unsigned char *bbase = (unsigned char *)lds_raw +
                            (lds_core_bytes(a) + kBatchBytes) * (size_t)wave + lds_core_bytes(a);
     V *b_prop = (V *)bbase;
@@ -714,8 +713,10 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(KArgs a)
     const int N = I.N;
     const int nb = wd.hi - wd.lo;
     const int ilo = wd.lo;
+    // spins in LDS for the segment, or read and written in place in HBM
     V *G = (V *)a.spins + I.cfg_off + (int64_t)st.cfg * N;
-    copy_spins<MODE>(S, G, N);
+    V *S = LDS_SPINS ? (V *)Ld.spins : G;
+    if (LDS_SPINS) copy_spins<MODE>(S, G, N);
     double *glng = a.lng + wd.bin_off;
     uint32_t *gH = a.hist + wd.bin_off;
     uint8_t *gvis = a.vis + wd.bin_off;
@@ -972,7 +973,7 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(KArgs a)
     }
     wave_sync();
 
-    copy_spins<MODE>(G, S, N);
+    if (LDS_SPINS) copy_spins<MODE>(G, S, N);
     for (int j = lane; j < nb; j += kWave) {
         const double v = Ld.lng[j];
         const bool vis = !__builtin_isnan(v);
@@ -1002,11 +1003,19 @@ int launch_init(const KArgs &a, int mode, hipStream_t s, size_t per_walker)
     const int wpb = a.walkers_per_block;
     const dim3 grid((a.n_walkers + wpb - 1) / wpb), block(kWave * wpb);
     const size_t lds = lds_bytes(a, per_walker);
-    switch (mode) {
-    case M_DET: hipLaunchKernelGGL(init_kernel<M_DET>, grid, block, lds, s, a); break;
-    case M_F64: hipLaunchKernelGGL(init_kernel<M_F64>, grid, block, lds, s, a); break;
-    case M_F32: hipLaunchKernelGGL(init_kernel<M_F32>, grid, block, lds, s, a); break;
-    default: return REWL_EINVAL;
+    if (a.spins_in_lds) {
+        switch (mode) {
+        case M_DET: hipLaunchKernelGGL((init_kernel<M_DET, true>), grid, block, lds, s, a); break;
+        case M_F64: hipLaunchKernelGGL((init_kernel<M_F64, true>), grid, block, lds, s, a); break;
+        case M_F32: hipLaunchKernelGGL((init_kernel<M_F32, true>), grid, block, lds, s, a); break;
+        default: return REWL_EINVAL;
+        }
+    } else {
+        switch (mode) {
+        case M_F64: hipLaunchKernelGGL((init_kernel<M_F64, false>), grid, block, lds, s, a); break;
+        case M_F32: hipLaunchKernelGGL((init_kernel<M_F32, false>), grid, block, lds, s, a); break;
+        default: return REWL_EINVAL;
+        }
     }
     return hipGetLastError() == hipSuccess ? REWL_OK : REWL_EDEVICE;
 }
@@ -1017,7 +1026,13 @@ int launch_sweep(const KArgs &a, int mode, hipStream_t s, size_t per_walker)
     const dim3 grid((a.n_walkers + wpb - 1) / wpb), block(kWave * wpb);
     const size_t lds = lds_bytes(a, per_walker);
     if (a.fast_q > 0 && mode != M_DET) {
-#define REWL_FAST(M, Qv, P2) hipLaunchKernelGGL((sweep_fast_kernel<M, Qv, P2>), grid, block, lds, s, a)
+#define REWL_FAST(M, Qv, P2)                                                                   \
+    do {                                                                                       \
+        if (a.spins_in_lds)                                                                    \
+            hipLaunchKernelGGL((sweep_fast_kernel<M, Qv, P2, true>), grid, block, lds, s, a);  \
+        else                                                                                   \
+            hipLaunchKernelGGL((sweep_fast_kernel<M, Qv, P2, false>), grid, block, lds, s, a); \
+    } while (0)
 #define REWL_FAST_Q(M, P2)                          \
     switch (a.fast_q) {                             \
     case 1: REWL_FAST(M, 1, P2); break;             \

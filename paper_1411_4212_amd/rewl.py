@@ -76,6 +76,8 @@ _SIGS = {
     "rewl_read_exchange_stats": [_vp, _i32, _P(_u64), _P(_u64), _i32],
     "rewl_read_step": [_vp, _P(_i64)],
     "rewl_set_trace": [_vp, _vp, _i64],
+    "rewl_set_launch": [_vp, _i32, _i32],
+    "rewl_get_launch": [_vp, _P(_i32), _P(_i32), _P(_i64)],
     "rewl_total_attempts": [_vp, _P(_u64), _P(_u64)],
 }
 for _name, _args in _SIGS.items():
@@ -237,6 +239,16 @@ def rewl_set_trace(ctx, dev_ptr, capacity):
     _call("rewl_set_trace", ctx, _vp(dev_ptr) if dev_ptr else None, capacity)
 
 
+def rewl_set_launch(ctx, walkers_per_block, residency=0):
+    _call("rewl_set_launch", ctx, walkers_per_block, residency)
+
+
+def rewl_get_launch(ctx):
+    w, r, b = _i32(), _i32(), _i64()
+    _call("rewl_get_launch", ctx, C.byref(w), C.byref(r), C.byref(b))
+    return dict(walkers_per_block=w.value, spins_in_lds=bool(r.value), lds_bytes_per_block=b.value)
+
+
 def rewl_total_attempts(ctx):
     a, b = _u64(), _u64()
     _call("rewl_total_attempts", ctx, C.byref(a), C.byref(b))
@@ -252,7 +264,8 @@ class Run:
       schedule: (flat_num, flat_den, lnf_init, lnf_final, exchange_interval, resync_interval)
     """
 
-    def __init__(self, instances, mode="fp64_det", device=0, stream=None, trace_cap=0):
+    def __init__(self, instances, mode="fp64_det", device=0, stream=None, trace_cap=0,
+                 walkers_per_block=1, residency=0):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", device)
@@ -276,6 +289,8 @@ class Run:
         self.bufs = [torch.empty(max(s, 256), dtype=torch.uint8, device=self.device)
                      for s in self.sizes]
         rewl_bind_buffers(self.ctx, [b.data_ptr() for b in self.bufs])
+        if walkers_per_block != 1 or residency != 0:
+            rewl_set_launch(self.ctx, walkers_per_block, residency)
         self.n_walkers = sum(q["h"] * q["m"] for q in self.inst)
         self.trace_cap = trace_cap
         self.trace_buf = None
@@ -346,6 +361,12 @@ class Run:
 
     def total_attempts(self):
         return rewl_total_attempts(self.ctx)
+
+    def set_launch(self, walkers_per_block, residency=0):
+        rewl_set_launch(self.ctx, walkers_per_block, residency)
+
+    def launch(self):
+        return rewl_get_launch(self.ctx)
 
     def trace(self, walker_global):
         self.torch.cuda.synchronize(self.device)

@@ -138,6 +138,44 @@ def c2(E_range=None):
                 schedule=(4, 5, 1.0, 2.0 ** -20, 10000, 100 * N), seed=0)
 
 
+def _bins_for(h, per_window=100, overlap=0.75):
+    """Global bin count that gives `per_window` bins per window."""
+    return int(round(per_window * (1 + (h - 1) * (1 - overlap))))
+
+
+def c4():
+    """bcc L=16 (8192 spins), eight shells J_n = exp(-0.6 (n-1)) (-1)^[n>5];
+    64 windows x 16 walkers, 100 bins per window, o = 0.75; ln f to 2^-20;
+    exchange every 1e4 moves; start from the ferromagnet."""
+    L, h, m = 16, 64, 16
+    N = 2 * L ** 3
+    Emin, Emax = paper_cut(L, J8)
+    return dict(name="bcc_L16_J8_64x16", lattice=("bcc", L, list(J8)),
+                windows=(Emin, Emax, _bins_for(h), h, 0.75, m),
+                schedule=(4, 5, 1.0, 2.0 ** -20, 10000, 100 * N), seed=0, init="ferro")
+
+
+def c5():
+    """bcc L=32 (65536 spins, configurations in HBM), the eight shells of
+    c4; 128 windows x 8 walkers, 100 bins per window; ln f to 2^-20;
+    exchange every 1e4 moves; start from the ferromagnet."""
+    L, h, m = 32, 128, 8
+    N = 2 * L ** 3
+    Emin, Emax = paper_cut(L, J8)
+    return dict(name="bcc_L32_J8_128x8", lattice=("bcc", L, list(J8)),
+                windows=(Emin, Emax, _bins_for(h), h, 0.75, m),
+                schedule=(4, 5, 1.0, 2.0 ** -20, 10000, 100 * N), seed=0, init="ferro")
+
+
+def init_spins(cfg):
+    """Starting configuration array for a workload (None = random start)."""
+    if cfg.get("init") == "ferro":
+        S = np.zeros((n_sites(cfg), 3))
+        S[:, 2] = 1.0
+        return S
+    return None
+
+
 def two_spins(n_bins=40, h=2, m=2):
     return dict(name="two_spins", lattice=("explicit", 2, [0], [1], [1.0]),
                 windows=(-1.0, 1.0, n_bins, h, 0.75, m),

@@ -21,14 +21,26 @@ def oracle_from(cfg, threads=4, trace=0, check_energy=False):
     return o
 
 
-def gpu_from(cfgs, mode, trace=0, seed=None):
+def gpu_from(cfgs, mode, trace=0, seed=None, walkers_per_block=1, residency=0):
+    import numpy as np
     from paper_1411_4212_amd.rewl import Run
+    from paper_1411_4212_amd.workloads import init_spins
     if isinstance(cfgs, dict):
         cfgs = [cfgs]
     r = Run([dict(lattice=c["lattice"], windows=c["windows"], schedule=c["schedule"])
-             for c in cfgs], mode=mode, trace_cap=trace)
-    r.init(cfgs[0]["seed"] if seed is None else seed)
+             for c in cfgs], mode=mode, trace_cap=trace, walkers_per_block=walkers_per_block,
+            residency=residency)
+    starts = [init_spins(c) for c in cfgs]
+    if all(s is None for s in starts):
+        init = None
+    else:
+        init = np.concatenate([s if s is not None else _random_unit(c) for s, c in zip(starts, cfgs)])
+    r.init(cfgs[0]["seed"] if seed is None else seed, init)
     return r
+
+
+def _random_unit(cfg):
+    raise ValueError("mixing random and given starts is not supported in tests")
 
 
 def joined_lng(read_lng, read_vis, window, h, m):

@@ -79,3 +79,60 @@ def test_fast_matches_oracle_early_trajectory():
         agree += k
         assert k >= 150, (w, k)
     assert agree >= 700
+
+
+@pytest.mark.parametrize("mode", ["fp32_de", "fp64"])
+def test_launch_shapes_bit_identical(mode):
+    """Configurations in LDS or read in place from HBM, one or four walkers
+    per workgroup: the same arithmetic on the same streams, so every state,
+    ln g and configuration agrees bit for bit after 6 segments."""
+    from paper_1411_4212_amd import workloads
+    from helpers import bits
+    cfg = workloads.c2()
+    runs = []
+    for wpb, res in [(1, 1), (1, 2), (3, 1), (4, 2)]:
+        _say("c2", mode, "wpb", wpb, "residency", res)
+        g = gpu_from(cfg, mode, walkers_per_block=wpb, residency=res)
+        assert g.launch()["walkers_per_block"] == wpb
+        assert g.launch()["spins_in_lds"] == (res == 1)
+        g.run(6)
+        runs.append(g)
+    ref = runs[0]
+    for g in runs[1:]:
+        for w in range(ref.n_walkers):
+            a, b = ref.walker(0, w), g.walker(0, w)
+            assert a == b, w
+            assert np.array_equal(bits(ref.lng(0, w)), bits(g.lng(0, w))), w
+            assert np.array_equal(ref.hist(0, w), g.hist(0, w)), w
+        for c in range(0, ref.n_walkers, 17):
+            assert np.array_equal(bits(ref.config(0, c)), bits(g.config(0, c))), c
+
+
+def test_hbm_L32_invariants():
+    """bcc L=32 (65536 spins, configurations in HBM) with the eight-shell
+    couplings, a slice of 2 windows per instance start from the ferromagnet:
+    two segments later every walker's running energy equals the FP64 energy
+    of its configuration (oracle energy function) within FP32 drift."""
+    import oracle
+    from paper_1411_4212_amd import workloads
+    cfg = workloads.c5()
+    Emin, Emax, B, h, o, m = cfg["windows"]
+    # the two lowest windows of the full layout
+    wl = round(B / (1 + (h - 1) * (1 - o)))
+    lo1 = round((B - wl) / (h - 1))
+    de = (Emax - Emin) / B
+    sub = dict(cfg, windows=(Emin, Emin + (lo1 + wl) * de, lo1 + wl, 2, o, 4))
+    _say("L32 hbm")
+    g = gpu_from(sub, "fp32_de")
+    assert not g.launch()["spins_in_lds"]
+    g.run(2)
+    lat = cfg["lattice"]
+    orc = oracle.Oracle(L=lat[1], J=lat[2])
+    for w in range(g.n_walkers):
+        st = g.walker(0, w)
+        assert st["attempts"] == 2 * cfg["schedule"][4]
+        S = g.config(0, st["config"])
+        Ef = orc.energy(S)
+        assert abs(Ef - st["E"]) < 0.05, (w, Ef, st["E"])
+        lo, hi = g.window(0, w)
+        assert lo <= st["bin"] < hi
