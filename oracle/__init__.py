@@ -56,6 +56,8 @@ def lib():
         L.orc_set_trace.argtypes = [vp, i64]
         L.orc_wl_accept_prob.argtypes = [dbl, dbl]
         L.orc_wl_accept_prob.restype = dbl
+        L.orc_wl_accept_prob_q.argtypes = [dbl, dbl, dbl, dbl]
+        L.orc_wl_accept_prob_q.restype = dbl
         L.orc_re_accept_prob.argtypes = [dbl, dbl, dbl, dbl]
         L.orc_re_accept_prob.restype = dbl
         L.orc_init.argtypes = [vp, u32, P(dbl)]
@@ -101,6 +103,10 @@ def exp_det(x):
 
 def wl_accept_prob(lng_a, lng_b):
     return lib().orc_wl_accept_prob(float(lng_a), float(lng_b))
+
+
+def wl_accept_prob_q(lng_a, lng_b, lnq_old, lnq_new):
+    return lib().orc_wl_accept_prob_q(float(lng_a), float(lng_b), float(lnq_old), float(lnq_new))
 
 
 def re_accept_prob(lngi_a, lngi_b, lngj_b, lngj_a):

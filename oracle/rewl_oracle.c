@@ -532,6 +532,19 @@ double orc_wl_accept_prob(double lng_a, double lng_b)
     return lr >= 0.0 ? 1.0 : orc_exp_det(lr);
 }
 
+/* Wang-Landau acceptance with an asymmetric proposal q(.|x) whose input x
+ * does not depend on the moved spin: ln of g(E_A) q(S_i|x) / (g(E_B) q(S'|x)) */
+static double wl_log_ratio_q(double lng_a, double lng_b, double lnq_old, double lnq_new)
+{
+    return (lng_a - lng_b) + (lnq_old - lnq_new);
+}
+
+double orc_wl_accept_prob_q(double lng_a, double lng_b, double lnq_old, double lnq_new)
+{
+    double lr = wl_log_ratio_q(lng_a, lng_b, lnq_old, lnq_new);
+    return lr >= 0.0 ? 1.0 : orc_exp_det(lr);
+}
+
 double orc_re_accept_prob(double lngi_a, double lngi_b, double lngj_b, double lngj_a)
 {
     double lr = re_log_ratio(lngi_a, lngi_b, lngj_b, lngj_a);

@@ -391,3 +391,41 @@ def test_schedule_and_thread_independence(oracle_mod):
     assert cfgs == list(range(a.W))
     att, acc = a.exchange_stats()
     assert att.sum() > 0 and acc.sum() > 0
+
+
+def test_detailed_balance_learned_proposal(oracle_mod):
+    """Exhaustive detailed balance for an asymmetric proposal: 3 spins on the
+    icosahedron directions, the new direction drawn from a categorical q that
+    depends on the site's neighbour field (not on the moved spin), accepted
+    by the oracle's q-ratio acceptance; pi ~ 1/g~(E) is reversible."""
+    D = _icosahedron()
+    nd = len(D)
+    n = 3
+    pairs = [(0, 1, 1.0), (1, 2, 0.7), (0, 2, -0.45)]
+    o = oracle_mod.Oracle(explicit=(n, [p[0] for p in pairs], [p[1] for p in pairs],
+                                    [p[2] for p in pairs]))
+    idx = np.array(np.meshgrid(*[np.arange(nd)] * n, indexing="ij")).reshape(n, -1).T
+    E = np.array([o.energy(D[s]) for s in idx])
+    Emin, Emax, B = E.min() - 1e-9, E.max() + 1e-9, 7
+    bins = np.floor((E - Emin) * (B / (Emax - Emin))).astype(int)
+    rng = np.random.default_rng(2)
+    lng = rng.normal(scale=2.0, size=B)
+    pw = nd ** np.arange(n)
+    worst = 0.0
+    for X in range(len(idx)):
+        S = D[idx[X]]
+        for i in range(n):
+            h = o.local_field(S, i)
+            logits = 2.5 * (D @ h)             # favours directions along the field
+            lq = logits - np.log(np.sum(np.exp(logits)))
+            for d in range(nd):
+                Yi = idx[X].copy()
+                Yi[i] = d
+                Y = int(Yi @ pw)
+                old = idx[X][i]
+                pf = oracle_mod.wl_accept_prob_q(lng[bins[X]], lng[bins[Y]], lq[old], lq[d])
+                pb = oracle_mod.wl_accept_prob_q(lng[bins[Y]], lng[bins[X]], lq[d], lq[old])
+                fwd = -lng[bins[X]] + lq[d] + np.log(pf)
+                bwd = -lng[bins[Y]] + lq[old] + np.log(pb)
+                worst = max(worst, abs(fwd - bwd))
+    assert worst < 1e-12
