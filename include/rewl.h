@@ -240,6 +240,66 @@ rewl_status rewl_read_step(rewl_ctx *ctx, int64_t *step_out);
  * off.  Call before rewl_init_walkers. */
 rewl_status rewl_set_trace(rewl_ctx *ctx, void *dev_records, int64_t capacity);
 
+/* ------------------------------------------------------------------------
+ * Learned proposal (an extension; the paper's trial move is a uniform new
+ * direction, Sec. simulation details).  The new direction is drawn from a
+ * mixture of three von Mises-Fisher densities and an eps = 0.05 uniform
+ * part, q(s|x), whose parameters an MLP 4 -> 64 -> 64 -> 12 (ReLU) computes
+ * from x = (h / h_s, e_w): h the local field at the site (without the site's
+ * own spin), h_s = sum_n z_n |J_n|, e_w the window centre energy per spin in
+ * units of h_s / 2.  Acceptance min(1, g(E_A) q(S_i|x) / (g(E_B) q(S'|x)))
+ * keeps the Wang-Landau walk exact.  Inference uses BF16 MFMA with FP32
+ * accumulation; training FP32.  Parameters: one FP32 vector of
+ * rewl_mlp_param_count() values in the order W1[64][4], b1[64], W2[64][64],
+ * b2[64], W3[12][64], b3[12]; outputs 4c..4c+3 are (v_c, a_c) of component c
+ * with kappa_c = clip(|v_c|, 1e-3, 1e3), mu_c = v_c/|v_c|, alpha = softmax(a).
+ * Training records are 8 floats: x0..x3, s0..s2 (unit spin), unused.
+ * ------------------------------------------------------------------------ */
+int32_t rewl_mlp_param_count(void);
+
+/* Bytes of the packed (per-lane BF16 MFMA layout) network. */
+size_t rewl_mlp_packed_bytes(void);
+
+/* Device workspace bytes for rewl_mlp_train (batch) or rewl_mlp_loss_grad (n). */
+rewl_status rewl_mlp_workspace_bytes(int64_t max_batch, size_t *bytes);
+
+/* Pack FP32 parameters (device) into the inference layout (device). */
+rewl_status rewl_mlp_pack(const float *dev_params, void *dev_packed, void *hip_stream);
+
+/* Evaluate the packed network on n inputs (device arrays): x[n][4], s[n][3],
+ * uniforms u[n][3] = (u_mix, u_w, u_phi) in [0,1) (u_w > 0), uniform
+ * directions udir[n][3]; writes ln q(s|x), a draw s' ~ q(.|x) and ln q(s'|x). */
+rewl_status rewl_mlp_eval(const void *dev_packed, const float *dev_x, const float *dev_s,
+                          const float *dev_u, const float *dev_udir, float *dev_lnq_s,
+                          float *dev_sample, float *dev_lnq_sample, int64_t n, void *hip_stream);
+
+/* Mean negative log-likelihood of n records and its gradient (device),
+ * FP32, summed in a fixed order (deterministic).  Synchronises the stream. */
+rewl_status rewl_mlp_loss_grad(const float *dev_records, int64_t n, const float *dev_params,
+                               float *dev_grad, double *loss_out, void *dev_workspace,
+                               void *hip_stream);
+
+/* Adam (lr, beta 0.9/0.999) on minibatches of `batch` records drawn with
+ * replacement by Philox(seed); epochs x (n / batch) steps; parameters updated
+ * in place (device); loss_per_epoch (host, optional) gets each epoch's mean
+ * minibatch loss.  Synchronises the stream. */
+rewl_status rewl_mlp_train(const float *dev_records, int64_t n, int32_t epochs, int32_t batch,
+                           float lr, uint64_t seed, float *dev_params, void *dev_workspace,
+                           float *loss_per_epoch, void *hip_stream);
+
+/* Proposal of a context: kind 0 = uniform direction, 1 = learned (FP32
+ * parameters on the device, packed into the context).  FP32_DE mode, bcc
+ * lattices. */
+rewl_status rewl_set_proposal(rewl_ctx *ctx, int32_t kind, const float *dev_params);
+
+/* Record (x, S_i) of every every_k-th trial move (before the move) into
+ * dev_records[walker][capacity_per_walker][8] (device, caller-owned, walker
+ * global index in instance order); NULL switches recording off.  Uniform
+ * proposal, fast kernel.  rewl_read_harvest_counts gives records per walker. */
+rewl_status rewl_set_harvest(rewl_ctx *ctx, float *dev_records, int64_t capacity_per_walker,
+                             int32_t every_k);
+rewl_status rewl_read_harvest_counts(rewl_ctx *ctx, int64_t *counts, int32_t cap);
+
 /* Totals over all walkers of the context (synchronising). */
 rewl_status rewl_total_attempts(rewl_ctx *ctx, uint64_t *attempts, uint64_t *accepts);
 

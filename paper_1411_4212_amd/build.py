@@ -5,8 +5,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librewl.so")
-SOURCES = ["rewl_kernels.hip", "rewl_api.cpp"]
-HEADERS = ["rewl_device.h", "rewl_internal.h"]
+SOURCES = ["rewl_kernels.hip", "rewl_mlp.hip", "rewl_api.cpp"]
+HEADERS = ["rewl_device.h", "rewl_internal.h", "rewl_mlp_device.h"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

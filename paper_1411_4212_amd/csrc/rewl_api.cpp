@@ -82,6 +82,8 @@ std::vector<ShellVec> bcc_shell_vectors(int n_shells)
 
 }  // namespace
 
+rewl_status rewl::report_error(rewl_status code, const char *msg) { return fail(code, msg); }
+
 struct rewl_ctx {
     int32_t device = 0;
     hipStream_t stream = nullptr;
@@ -110,6 +112,11 @@ struct rewl_ctx {
     int32_t residency_req = 0;   // 0 auto, 1 LDS, 2 HBM
     int32_t wpb_req = 1;
     int32_t spins_in_lds = 1;
+    size_t off_mlp = 0;          // packed learned-proposal network in PARAMS
+    int32_t proposal = 0;        // 0 uniform, 1 learned
+    float *harvest = nullptr;
+    int64_t harvest_cap = 0;
+    int32_t harvest_every = 1;
     int32_t wpb = 1;
     int32_t fast_q = 0;
     int32_t all_pow2 = 0;
@@ -161,6 +168,10 @@ KArgs make_args(rewl_ctx *c)
     a.walkers_per_block = c->wpb;
     a.lds_spins_bytes = c->spins_in_lds ? c->lds_spins_bytes : 0;
     a.spins_in_lds = c->spins_in_lds;
+    a.mlp = c->proposal == 1 ? (const void *)(P + c->off_mlp) : nullptr;
+    a.harvest = c->harvest;
+    a.harvest_cap = c->harvest_cap;
+    a.harvest_every = c->harvest_every;
     a.lds_bins = c->lds_bins;
     a.fast_q = c->fast_q;
     a.all_pow2 = c->all_pow2;
@@ -173,7 +184,7 @@ KArgs make_args(rewl_ctx *c)
 rewl_status plan_launch(rewl_ctx *c)
 {
     const size_t bins = ((size_t)c->lds_bins * 13u + 15) & ~(size_t)15;
-    const size_t batch = 64 * 48;
+    const size_t batch = 64 * 64;
     const size_t with_spins = (((size_t)c->lds_spins_bytes + (size_t)c->lds_bins * 13u + 15) & ~(size_t)15) + batch;
     const size_t without = bins + batch;
     const size_t cap = 160 * 1024;
@@ -291,6 +302,21 @@ rewl_status finalize(rewl_ctx *c)
             c->tdeg.insert(c->tdeg.end(), deg.begin(), deg.end());
         }
         if (d.z > REWL_MAX_DEGREE) return fail(REWL_ERANGE, "more than 128 neighbours per site");
+        {
+            // h_s = sum of |J| over a site's neighbours (largest over sites)
+            double hs = 0.0;
+            if (q.lattice == LAT_BCC) {
+                for (int k = 0; k < d.z; ++k) hs += std::fabs(c->slots[d.slot_off + k].Jd);
+            } else {
+                std::vector<double> acc(q.N, 0.0);
+                for (size_t p = 0; p < q.pi.size(); ++p) {
+                    acc[q.pi[p]] += std::fabs(q.pJ[p]);
+                    acc[q.pj[p]] += std::fabs(q.pJ[p]);
+                }
+                for (double v : acc) hs = std::max(hs, v);
+            }
+            d.inv_hs = hs > 0.0 ? (float)(1.0 / hs) : 0.f;
+        }
         // windows
         q.lo.assign(q.h, 0);
         q.hi.assign(q.h, 0);
@@ -315,6 +341,12 @@ rewl_status finalize(rewl_ctx *c)
                 wd.bin_off = bin_off;
                 wd.stream = (uint32_t)(walker_base + k * q.m + r);
                 wd.local = k * q.m + r;
+                {
+                    const double de = (q.Emax - q.Emin) / (double)q.B;
+                    const double ec = q.Emin + 0.5 * (double)(q.lo[k] + q.hi[k]) * de;
+                    const double hs = d.inv_hs > 0.f ? 1.0 / (double)d.inv_hs : 1.0;
+                    wd.e_w = (float)(ec / ((double)q.N * 0.5 * hs));
+                }
                 bin_off += wd.hi - wd.lo;
                 c->wdesc.push_back(wd);
             }
@@ -365,6 +397,8 @@ rewl_status finalize(rewl_ctx *c)
     o = align256(o + sizeof(int32_t) * c->tnbr.size());
     c->off_tJ = o;
     o = align256(o + sizeof(double) * c->tJ.size());
+    c->off_mlp = o;
+    o = align256(o + rewl_mlp_packed_bytes());
     c->off_init = o;
     int64_t init_doubles = 0;
     for (auto &q : c->inst) init_doubles += 3 * (int64_t)q.N;
@@ -655,6 +689,54 @@ rewl_status rewl_get_launch(rewl_ctx *ctx, int32_t *walkers_per_block, int32_t *
     *walkers_per_block = ctx->wpb;
     *spins_in_lds = ctx->spins_in_lds;
     *lds_bytes_per_block = (int64_t)(((ctx->lds_per_walker + 15) & ~(size_t)15) * (size_t)ctx->wpb);
+    return REWL_OK;
+}
+
+rewl_status rewl_set_proposal(rewl_ctx *ctx, int32_t kind, const float *dev_params)
+{
+    if (!ctx) return fail(REWL_EINVAL, "null context");
+    if (ctx->stage < 2) return fail(REWL_ESTATE, "bind buffers first");
+    if (kind == 0) {
+        ctx->proposal = 0;
+        return REWL_OK;
+    }
+    if (kind != 1 || !dev_params) return fail(REWL_EINVAL, "kind must be 0 (uniform) or 1 (learned, with parameters)");
+    if (ctx->mode != REWL_MODE_FP32_DE || ctx->fast_q == 0)
+        return fail(REWL_EUNSUPPORTED, "the learned proposal runs in FP32_DE mode on bcc lattices");
+    if (ctx->harvest) return fail(REWL_EUNSUPPORTED, "harvesting records needs the uniform proposal");
+    int rc = launch_mlp_pack(dev_params, (unsigned char *)ctx->buf[REWL_BUF_PARAMS] + ctx->off_mlp, ctx->stream);
+    if (rc) return fail(rc, "pack kernel launch failed");
+    ctx->proposal = 1;
+    return REWL_OK;
+}
+
+rewl_status rewl_set_harvest(rewl_ctx *ctx, float *dev_records, int64_t capacity_per_walker, int32_t every_k)
+{
+    if (!ctx) return fail(REWL_EINVAL, "null context");
+    if (ctx->stage < 1) return fail(REWL_ESTATE, "call rewl_query_sizes first");
+    if (!dev_records) {
+        ctx->harvest = nullptr;
+        ctx->harvest_cap = 0;
+        return REWL_OK;
+    }
+    if (capacity_per_walker < 1 || every_k < 1) return fail(REWL_EINVAL, "capacity and interval must be positive");
+    if (ctx->fast_q == 0 || ctx->proposal != 0)
+        return fail(REWL_EUNSUPPORTED, "harvesting needs the fast kernel and the uniform proposal");
+    ctx->harvest = dev_records;
+    ctx->harvest_cap = capacity_per_walker;
+    ctx->harvest_every = every_k;
+    return REWL_OK;
+}
+
+rewl_status rewl_read_harvest_counts(rewl_ctx *ctx, int64_t *counts, int32_t cap)
+{
+    if (!ctx || !counts) return fail(REWL_EINVAL, "null argument");
+    if (ctx->stage < 3) return fail(REWL_ESTATE, "walkers not initialised");
+    rewl_status st = sync_check(ctx);
+    if (st) return st;
+    std::vector<WalkerState> ws(ctx->n_walkers);
+    HIP_TRY(hipMemcpy(ws.data(), ctx->buf[REWL_BUF_STATE], sizeof(WalkerState) * ws.size(), hipMemcpyDeviceToHost));
+    for (int w = 0; w < ctx->n_walkers && w < cap; ++w) counts[w] = (int64_t)ws[w].harvested;
     return REWL_OK;
 }
 

@@ -247,7 +247,10 @@ __device__ __forceinline__ int bcc_neighbour(int site, int L, float invL, const 
     int q = divmod_small(site, L, invL, x);
     q = divmod_small(q, L, invL, y);
     const int s = divmod_small(q, L, invL, z);
-    int nx = x + sl.d[s][0], ny = y + sl.d[s][1], nz = z + sl.d[s][2];
+    // selects rather than an indexed load of the slot (keeps it in registers)
+    int nx = x + (s ? sl.d[1][0] : sl.d[0][0]);
+    int ny = y + (s ? sl.d[1][1] : sl.d[0][1]);
+    int nz = z + (s ? sl.d[1][2] : sl.d[0][2]);
     nx += nx < 0 ? L : 0;
     nx -= nx >= L ? L : 0;
     ny += ny < 0 ? L : 0;

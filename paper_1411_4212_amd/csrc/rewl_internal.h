@@ -17,7 +17,8 @@ enum Tag : uint32_t {
     TAG_INIT_SPHERE = 3,   // drive into the window: direction
     TAG_EXCH = 4,          // replica-exchange acceptance uniform
     TAG_PERM = 5,          // pairing permutation of an exchange step
-    TAG_INIT_CONFIG = 6    // random initial configuration
+    TAG_INIT_CONFIG = 6,   // random initial configuration
+    TAG_LEARNED = 7        // learned proposal: mixture choice, w and azimuth uniforms
 };
 
 // Read-only description of one REWL instance.
@@ -25,7 +26,8 @@ struct InstDesc {
     int32_t N, L, lattice, z;          // sites, cells per edge, lattice kind, neighbours/site
     int32_t h, m, B, walker_base;      // windows, walkers/window, global bins, first walker
     int32_t n_walkers, slot_off, flat_num, flat_den;
-    int32_t xstat_off, nb_max, deg_off, pad1;   // deg_off: first entry in the degree table
+    int32_t xstat_off, nb_max, deg_off;   // deg_off: first entry in the degree table
+    float inv_hs;                         // 1 / sum_n z_n |J_n| (learned-proposal features)
     double Emin, inv_de, lnf_final, lnf_init;
     int64_t seg_len, resync;
     int64_t cfg_off;                   // spin element offset of configuration 0
@@ -39,6 +41,8 @@ struct WalkerDesc {
     int64_t bin_off;                   // element offset of its window in LNG/HIST/VISITED
     uint32_t stream;                   // global walker id: second Philox key word
     int32_t local;                     // index within its instance
+    float e_w;                         // window centre energy per spin / (h_s / 2)
+    int32_t pad;
 };
 
 // Dynamic per-walker state (device).
@@ -46,6 +50,7 @@ struct WalkerState {
     double E, lnf, max_drift;
     int32_t bin, cfg, iter, done, nvis, status;
     uint64_t attempts, accepts, oow;
+    uint64_t harvested;                // training records written
 };
 
 // One bcc neighbour slot: cell displacement for a site on sublattice 0 and
@@ -93,10 +98,18 @@ struct KArgs {
     int32_t fast_q;            // >0: fast sweep kernel with this many neighbour slots per lane
     int32_t all_pow2;          // every instance has L a power of two
     int32_t spins_in_lds;      // 1: configurations staged in LDS; 0: read in place from HBM
-    int32_t pad2;
+    int32_t harvest_every;     // record every k-th move
+    const void *mlp;           // packed learned-proposal network (nullptr: uniform proposal)
+    float *harvest;            // training records [walker][harvest_cap][8] (nullptr: off)
+    int64_t harvest_cap;
 };
 
 constexpr int kWave = 64;
+
+// Record an error for rewl_last_error() and return `code`.
+rewl_status report_error(rewl_status code, const char *msg);
+
+int launch_mlp_pack(const float *dev_params, void *dev_packed, hipStream_t s);
 
 // Kernel launchers (rewl_kernels.hip).
 int launch_init(const KArgs &a, int mode, hipStream_t s, size_t lds_per_walker);

@@ -16,6 +16,7 @@
 
 #include "rewl_device.h"
 #include "rewl_internal.h"
+#include "rewl_mlp_device.h"
 
 namespace rewl {
 
@@ -52,7 +53,7 @@ struct WalkerLds {
 
 // Per-walker LDS: spins | ln g (FP64) | H (u32) | visited (u8) | look-ahead
 // batch of 64 trial moves (fast kernel).
-constexpr size_t kBatchBytes = 64 * (32 + 4 + 4 + 8);
+constexpr size_t kBatchBytes = 64 * (32 + 4 + 4 + 8 + 16);
 
 __device__ __forceinline__ size_t lds_core_bytes(const KArgs &a)
 {
@@ -687,7 +688,7 @@ struct FastLat {
     uint32_t M, Hm;          // SWAR masks: field bits below the top bit / top bits
 };
 
-template <int MODE, int Q, bool POW2, bool LDS_SPINS>
+template <int MODE, int Q, bool POW2, bool LDS_SPINS, bool LEARNED>
 __global__ void __launch_bounds__(256) sweep_fast_kernel(KArgs a)
 {
     using T = typename Spin<MODE>::T;
@@ -709,6 +710,7 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(KArgs a)
     int32_t *b_site = (int32_t *)(bbase + 64 * sizeof(V));
     int32_t *b_code = b_site + 64;
     double *b_lnu = (double *)(b_code + 64);
+    float4 *b_ul = (float4 *)(b_lnu + 64);      // learned proposal: (u_mix, u_w, u_phi, -)
 
     const int N = I.N;
     const int nb = wd.hi - wd.lo;
@@ -743,12 +745,14 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(KArgs a)
     T Jq[Q];
     {
         const BccSlot *slots = a.slots + I.slot_off;
+#pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int k = q * 16 + r;
             BccSlot sl{};
             if (k < I.z) sl = slots[k];
             Jq[q] = (k < I.z) ? ((MODE == M_F32) ? (T)sl.Jf : (T)sl.Jd) : (T)0;
             flipb[q] = sl.flip;
+#pragma unroll
             for (int sb = 0; sb < 2; ++sb) {
                 const uint32_t ox = (uint32_t)((sl.d[sb][0] + fl.L) % fl.L);
                 const uint32_t oy = (uint32_t)((sl.d[sb][1] + fl.L) % fl.L);
@@ -783,6 +787,15 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(KArgs a)
 
     int nidx[Q];
     T dEv = 0;
+    T hx_k = 0, hy_k = 0, hz_k = 0;          // this lane's group field (harvest)
+    V si_k{};
+    float lnqr_v = 0.f;                        // learned: ln q(S_i) - ln q(S'), lane = move
+    float psx = 0.f, psy = 0.f, psz = 0.f;     // learned: proposal of move p + lane
+    const float inv_hs = I.inv_hs, e_w = wd.e_w;
+    mlp::Lane Wl;
+    if constexpr (LEARNED) Wl = ((const mlp::Lane *)a.mlp)[lane];
+    const bool harvesting = a.harvest != nullptr && !LEARNED;
+    uint64_t hcount = st.harvested;
     // gather + field + dE of the move held by this lane's group (batch slot p + grp)
     auto fields = [&](int p) {
         const int e = p + grp;
@@ -815,10 +828,38 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(KArgs a)
             pz = fma_t<T>(Jq[q], s.z, pz);
         }
         const T hx = row_sum16(px), hy = row_sum16(py), hz = row_sum16(pz);
-        if constexpr (MODE == M_F32) {
-            dEv = -__builtin_fmaf(pr.z - si.z, hz, __builtin_fmaf(pr.y - si.y, hy, (pr.x - si.x) * hx));
+        hx_k = hx;
+        hy_k = hy;
+        hz_k = hz;
+        si_k = si;
+        if constexpr (!LEARNED) {
+            if constexpr (MODE == M_F32) {
+                dEv = -__builtin_fmaf(pr.z - si.z, hz, __builtin_fmaf(pr.y - si.y, hy, (pr.x - si.x) * hx));
+            } else {
+                dEv = -(((pr.x - si.x) * hx + (pr.y - si.y) * hy) + (pr.z - si.z) * hz);
+            }
         } else {
-            dEv = -(((pr.x - si.x) * hx + (pr.y - si.y) * hy) + (pr.z - si.z) * hz);
+            // lane m < 4 takes move p + m: its field and current spin from group m
+            const int mv = lane & 3;
+            auto pick = [&](float v) {
+                const float v0 = readlane_f(v, 0), v1 = readlane_f(v, 16), v2 = readlane_f(v, 32),
+                            v3 = readlane_f(v, 48);
+                return (mv & 2) ? ((mv & 1) ? v3 : v2) : ((mv & 1) ? v1 : v0);
+            };
+            const float hm0 = pick((float)hx), hm1 = pick((float)hy), hm2 = pick((float)hz);
+            const float sm0 = pick((float)si.x), sm1 = pick((float)si.y), sm2 = pick((float)si.z);
+            const mlp::bf16x8 xb = mlp::input_operand(hm0 * inv_hs, hm1 * inv_hs, hm2 * inv_hs, e_w, lane < 4);
+            const mlp::f32x4 o = mlp::forward(Wl, xb);
+            float out[12];
+            mlp::gather_outputs(o, out);
+            if (lane < 4) {
+                const mlp::Mix mx = mlp::mixture(out);
+                const float4 uu = b_ul[p + lane];
+                const V ud = b_prop[p + lane];
+                mlp::sample(mx, uu.x, uu.y, uu.z, (float)ud.x, (float)ud.y, (float)ud.z, psx, psy, psz);
+                lnqr_v = mlp::log_q(mx, sm0, sm1, sm2) - mlp::log_q(mx, psx, psy, psz);
+                dEv = (T)(-__builtin_fmaf(psz - sm2, hm2, __builtin_fmaf(psy - sm1, hm1, (psx - sm0) * hm0)));
+            }
         }
     };
 
@@ -851,6 +892,12 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(KArgs a)
             b_code[lane] = code;
             my_site = site;
             my_lnu = log(u);
+            if constexpr (LEARNED) {
+                const U4 ru = draw(a.seed, wd.stream, nn, 0u, TAG_LEARNED);
+                b_ul[lane] = make_float4((float)(ru.x >> 8) * (1.0f / 16777216.0f),
+                                         ((float)(ru.y >> 8) + 0.5f) * (1.0f / 16777216.0f),
+                                         (float)(ru.z >> 8) * (1.0f / 16777216.0f), 0.f);
+            }
         }
         wave_sync();
         const int nvalid = (int)((n_end - n0) < 64 ? (n_end - n0) : 64);
@@ -864,7 +911,21 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(KArgs a)
                     stale = false;
                 }
                 const uint64_t n = n0 + (uint64_t)(p + g);
-                const double dE = (double)readlane_t<T>(dEv, 16 * g);
+                const double dE = (double)readlane_t<T>(dEv, LEARNED ? g : 16 * g);
+                const double lnqr = LEARNED ? (double)readlane_f(lnqr_v, g) : 0.0;
+                if (harvesting && (n % (uint64_t)a.harvest_every) == 0 && hcount < (uint64_t)a.harvest_cap) {
+                    // training record of this move, taken before the move
+                    const float rx = readlane_f((float)hx_k, 16 * g), ry = readlane_f((float)hy_k, 16 * g),
+                                rz = readlane_f((float)hz_k, 16 * g);
+                    const float sx = readlane_f((float)si_k.x, 16 * g), sy = readlane_f((float)si_k.y, 16 * g),
+                                sz = readlane_f((float)si_k.z, 16 * g);
+                    if (lane == 0) {
+                        float4 *rec = (float4 *)(a.harvest + ((int64_t)w * a.harvest_cap + (int64_t)hcount) * 8);
+                        rec[0] = make_float4(rx * inv_hs, ry * inv_hs, rz * inv_hs, e_w);
+                        rec[1] = make_float4(sx, sy, sz, 0.f);
+                    }
+                    ++hcount;
+                }
                 const int site = __builtin_amdgcn_readlane(my_site, p + g);
                 const double lnu = readlane_d(my_lnu, p + g);
                 const double Eb = E + dE;
@@ -886,13 +947,24 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(KArgs a)
                         }
                     }
                     if (!outside) {
-                        const double lr = cur - lnb;
+                        const double lr = (cur - lnb) + lnqr;
                         accept = (lr >= 0.0) || (lnu < lr);
                     }
                 }
                 oow += outside ? 1u : 0u;
                 if (accept) {
-                    if (lane == 16 * g) S[site] = b_prop[p + g];
+                    if constexpr (LEARNED) {
+                        if (lane == g) {
+                            V v;
+                            v.x = (T)psx;
+                            v.y = (T)psy;
+                            v.z = (T)psz;
+                            v.w = (T)0;
+                            S[site] = v;
+                        }
+                    } else {
+                        if (lane == 16 * g) S[site] = b_prop[p + g];
+                    }
                     E = Eb;
                     bin = bb;
                     cur = lnb;
@@ -987,6 +1059,7 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(KArgs a)
         st.attempts = n;
         st.accepts += acc_count;
         st.oow += oow;
+        st.harvested = hcount;
         if (!isfinite(E) || !isfinite(cur)) st.status = REWL_ENUMERIC;
         a.state[w] = st;
     }
@@ -1026,12 +1099,18 @@ int launch_sweep(const KArgs &a, int mode, hipStream_t s, size_t per_walker)
     const dim3 grid((a.n_walkers + wpb - 1) / wpb), block(kWave * wpb);
     const size_t lds = lds_bytes(a, per_walker);
     if (a.fast_q > 0 && mode != M_DET) {
-#define REWL_FAST(M, Qv, P2)                                                                   \
-    do {                                                                                       \
-        if (a.spins_in_lds)                                                                    \
-            hipLaunchKernelGGL((sweep_fast_kernel<M, Qv, P2, true>), grid, block, lds, s, a);  \
-        else                                                                                   \
-            hipLaunchKernelGGL((sweep_fast_kernel<M, Qv, P2, false>), grid, block, lds, s, a); \
+#define REWL_FAST(M, Qv, P2)                                                                          \
+    do {                                                                                              \
+        if (a.mlp && M == M_F32) {                                                                    \
+            if (a.spins_in_lds)                                                                       \
+                hipLaunchKernelGGL((sweep_fast_kernel<M_F32, Qv, P2, true, true>), grid, block, lds, s, a);  \
+            else                                                                                      \
+                hipLaunchKernelGGL((sweep_fast_kernel<M_F32, Qv, P2, false, true>), grid, block, lds, s, a); \
+        } else if (a.spins_in_lds) {                                                                  \
+            hipLaunchKernelGGL((sweep_fast_kernel<M, Qv, P2, true, false>), grid, block, lds, s, a);  \
+        } else {                                                                                      \
+            hipLaunchKernelGGL((sweep_fast_kernel<M, Qv, P2, false, false>), grid, block, lds, s, a); \
+        }                                                                                             \
     } while (0)
 #define REWL_FAST_Q(M, P2)                          \
     switch (a.fast_q) {                             \

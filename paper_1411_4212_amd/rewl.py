@@ -77,6 +77,14 @@ _SIGS = {
     "rewl_read_step": [_vp, _P(_i64)],
     "rewl_set_trace": [_vp, _vp, _i64],
     "rewl_set_launch": [_vp, _i32, _i32],
+    "rewl_set_proposal": [_vp, _i32, _vp],
+    "rewl_set_harvest": [_vp, _vp, _i64, _i32],
+    "rewl_read_harvest_counts": [_vp, _P(_i64), _i32],
+    "rewl_mlp_workspace_bytes": [_i64, _P(_sz)],
+    "rewl_mlp_pack": [_vp, _vp, _vp],
+    "rewl_mlp_eval": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp],
+    "rewl_mlp_loss_grad": [_vp, _i64, _vp, _vp, _P(C.c_double), _vp, _vp],
+    "rewl_mlp_train": [_vp, _i64, _i32, _i32, C.c_float, _u64, _vp, _vp, _P(C.c_float), _vp],
     "rewl_get_launch": [_vp, _P(_i32), _P(_i32), _P(_i64)],
     "rewl_total_attempts": [_vp, _P(_u64), _P(_u64)],
 }
@@ -84,12 +92,17 @@ for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
     _f.argtypes = _args
     _f.restype = C.c_int32
+_lib.rewl_mlp_param_count.argtypes = []
+_lib.rewl_mlp_param_count.restype = C.c_int32
+_lib.rewl_mlp_packed_bytes.argtypes = []
+_lib.rewl_mlp_packed_bytes.restype = C.c_size_t
 _lib.rewl_destroy.argtypes = [_vp]
 _lib.rewl_destroy.restype = None
 _lib.rewl_last_error.argtypes = []
 _lib.rewl_last_error.restype = C.c_char_p
 
-EXPORTED = list(_SIGS) + ["rewl_destroy", "rewl_last_error"]
+EXPORTED = list(_SIGS) + ["rewl_destroy", "rewl_last_error", "rewl_mlp_param_count",
+                          "rewl_mlp_packed_bytes"]
 
 
 def rewl_last_error():
@@ -249,6 +262,59 @@ def rewl_get_launch(ctx):
     return dict(walkers_per_block=w.value, spins_in_lds=bool(r.value), lds_bytes_per_block=b.value)
 
 
+def rewl_set_proposal(ctx, kind, dev_params_ptr=None):
+    _call("rewl_set_proposal", ctx, kind, _vp(dev_params_ptr) if dev_params_ptr else None)
+
+
+def rewl_set_harvest(ctx, dev_records_ptr, capacity_per_walker, every_k):
+    _call("rewl_set_harvest", ctx, _vp(dev_records_ptr) if dev_records_ptr else None,
+          capacity_per_walker, every_k)
+
+
+def rewl_read_harvest_counts(ctx, n_walkers):
+    out = np.zeros(n_walkers, dtype=np.int64)
+    _call("rewl_read_harvest_counts", ctx, out.ctypes.data_as(_P(_i64)), n_walkers)
+    return out
+
+
+def rewl_mlp_param_count():
+    return int(_lib.rewl_mlp_param_count())
+
+
+def rewl_mlp_packed_bytes():
+    return int(_lib.rewl_mlp_packed_bytes())
+
+
+def rewl_mlp_workspace_bytes(max_batch):
+    b = _sz()
+    _call("rewl_mlp_workspace_bytes", max_batch, C.byref(b))
+    return b.value
+
+
+def rewl_mlp_pack(dev_params, dev_packed, stream=0):
+    _call("rewl_mlp_pack", _vp(dev_params), _vp(dev_packed), _vp(stream))
+
+
+def rewl_mlp_eval(dev_packed, dev_x, dev_s, dev_u, dev_udir, dev_lnq_s, dev_sample, dev_lnq_sample,
+                  n, stream=0):
+    _call("rewl_mlp_eval", _vp(dev_packed), _vp(dev_x), _vp(dev_s), _vp(dev_u), _vp(dev_udir),
+          _vp(dev_lnq_s), _vp(dev_sample), _vp(dev_lnq_sample), n, _vp(stream))
+
+
+def rewl_mlp_loss_grad(dev_records, n, dev_params, dev_grad, dev_workspace, stream=0):
+    loss = C.c_double()
+    _call("rewl_mlp_loss_grad", _vp(dev_records), n, _vp(dev_params), _vp(dev_grad), C.byref(loss),
+          _vp(dev_workspace), _vp(stream))
+    return loss.value
+
+
+def rewl_mlp_train(dev_records, n, epochs, batch, lr, seed, dev_params, dev_workspace, stream=0):
+    losses = np.zeros(max(epochs, 1), dtype=np.float32)
+    _call("rewl_mlp_train", _vp(dev_records), n, epochs, batch, lr, seed, _vp(dev_params),
+          _vp(dev_workspace), losses.ctypes.data_as(_P(C.c_float)), _vp(stream))
+    return losses[:epochs]
+
+
 def rewl_total_attempts(ctx):
     a, b = _u64(), _u64()
     _call("rewl_total_attempts", ctx, C.byref(a), C.byref(b))
@@ -361,6 +427,27 @@ class Run:
 
     def total_attempts(self):
         return rewl_total_attempts(self.ctx)
+
+    def set_proposal(self, params=None):
+        """params: torch float32 tensor on the device (learned) or None (uniform)."""
+        if params is None:
+            rewl_set_proposal(self.ctx, 0, None)
+        else:
+            self._mlp_params = params
+            rewl_set_proposal(self.ctx, 1, params.data_ptr())
+
+    def set_harvest(self, capacity_per_walker, every_k):
+        self.harvest_cap = capacity_per_walker
+        self.harvest_buf = self.torch.zeros(self.n_walkers * capacity_per_walker * 8,
+                                            dtype=self.torch.float32, device=self.device)
+        rewl_set_harvest(self.ctx, self.harvest_buf.data_ptr(), capacity_per_walker, every_k)
+
+    def harvested(self):
+        """All harvested records as a (n, 8) float32 device tensor."""
+        counts = rewl_read_harvest_counts(self.ctx, self.n_walkers)
+        recs = self.harvest_buf.view(self.n_walkers, self.harvest_cap, 8)
+        parts = [recs[w, :int(c)] for w, c in enumerate(counts) if c > 0]
+        return self.torch.cat(parts) if parts else recs[:0, 0]
 
     def set_launch(self, walkers_per_block, residency=0):
         rewl_set_launch(self.ctx, walkers_per_block, residency)

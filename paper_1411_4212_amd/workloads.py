@@ -167,6 +167,25 @@ def c5():
                 schedule=(4, 5, 1.0, 2.0 ** -20, 10000, 100 * N), seed=0, init="ferro")
 
 
+def batched(n_instances=64):
+    """64 independent runs of uneven size in one context: bcc L in
+    {6, 8, 10, 12}, four sign-mixed shells J_n in [-0.2, 1.0), 8..32 windows x
+    4..8 walkers, 100 bins per window; FP32 dE.  Inputs come from
+    data/batched_instances.json (written by make_batched.py)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "batched_instances.json")
+    inst = json.load(open(path))["instances"][:n_instances]
+    out = []
+    for d in inst:
+        L, h, m = d["L"], d["h"], d["m"]
+        N = 2 * L ** 3
+        out.append(dict(name="batched_L%d_h%d_m%d" % (L, h, m), lattice=("bcc", L, list(d["J"])),
+                        windows=(d["E_min"], d["E_max"], _bins_for(h), h, 0.75, m),
+                        schedule=(4, 5, 1.0, 2.0 ** -20, 10000, 100 * N), seed=3))
+    return out
+
+
 def init_spins(cfg):
     """Starting configuration array for a workload (None = random start)."""
     if cfg.get("init") == "ferro":

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     txt = open(os.path.join(ROOT, "include", "rewl.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:rewl_status|void|const char \*)\s*\*?(rewl_\w+)\s*\(",
+    return sorted(set(re.findall(r"^\s*(?:rewl_status|void|const char \*|int32_t|size_t)\s*\*?(rewl_\w+)\s*\(",
                                  txt, re.M)))
 
 
