@@ -61,7 +61,7 @@ enum {
     REWL_ERANGE = -4,       /* a size exceeds a documented limit */
     REWL_EINIT = -5,        /* a walker could not be driven into its window */
     REWL_ENUMERIC = -6,     /* non-finite ln g or energy detected */
-    REWL_ECORRUPT = -7,     /* reserved */
+    REWL_ECORRUPT = -7,     /* checkpoint damaged or from another configuration */
     REWL_EUNSUPPORTED = -8  /* combination not implemented */
 };
 
@@ -199,6 +199,20 @@ rewl_status rewl_init_walkers(rewl_ctx *ctx, uint64_t seed, const double *init_s
  * Asynchronous. */
 rewl_status rewl_run(rewl_ctx *ctx, int64_t n_segments);
 
+/* The same walk as rewl_run(ctx, max_rounds) in ONE persistent launch
+ * (FP64 and FP32_DE modes on bcc lattices): each instance advances on its
+ * own, a round being a segment of each of its walkers followed by its
+ * exchange step, until it is done or has run max_rounds rounds; instances of
+ * uneven size therefore never wait for each other.  Wavefronts take walkers
+ * from a device work queue, and the last walker of an instance to finish a
+ * round runs the exchange.  The results are bit-identical to rewl_run's.
+ * The grid is as many blocks (of rewl_set_launch's walkers per block) as
+ * are resident at once, at most one walker per wavefront, and at most
+ * max_blocks if max_blocks > 0; *grid_out (may be NULL) receives it.  Synchronises the stream; REWL_EDEVICE if a bounded
+ * device wait ran out, REWL_ERANGE if max_rounds * walkers >= 2^31 - queue
+ * capacity, REWL_EUNSUPPORTED in FP64_DET mode or on explicit couplings. */
+rewl_status rewl_run_persistent(rewl_ctx *ctx, int64_t max_rounds, int32_t max_blocks, int32_t *grid_out);
+
 /* Enqueue the trial-move part of one segment only: exchange_interval trial
  * moves per walker, the resync when due and the flatness test, without the
  * exchange step (rewl_run = rewl_sweep + rewl_exchange, repeated).
@@ -223,6 +237,13 @@ rewl_status rewl_read_visited(rewl_ctx *ctx, int32_t inst, int32_t walker, uint8
                               int32_t cap, int32_t *n_out);
 rewl_status rewl_read_walker_state(rewl_ctx *ctx, int32_t inst, int32_t walker,
                                    rewl_walker_state *out);
+/* Overwrite a walker's ln g~ (and visited flags; NULL = all visited) for its
+ * window, min(cap, hi - lo) entries from `lng` (host).  With ln f ~ 0 and a
+ * flatness fraction of 1 this runs a fixed-weight (multicanonical) walk;
+ * it also restores a saved estimate.  Synchronises the stream. */
+rewl_status rewl_write_lng(rewl_ctx *ctx, int32_t inst, int32_t walker, const double *lng,
+                           const uint8_t *visited, int32_t cap);
+
 /* configuration `config` of instance inst as N*3 doubles */
 rewl_status rewl_read_config(rewl_ctx *ctx, int32_t inst, int32_t config, double *out,
                              int64_t cap);
@@ -299,6 +320,21 @@ rewl_status rewl_set_proposal(rewl_ctx *ctx, int32_t kind, const float *dev_para
 rewl_status rewl_set_harvest(rewl_ctx *ctx, float *dev_records, int64_t capacity_per_walker,
                              int32_t every_k);
 rewl_status rewl_read_harvest_counts(rewl_ctx *ctx, int64_t *counts, int32_t cap);
+
+/* Checkpoint / restore.  rewl_save writes every device buffer of the
+ * context (configurations, ln g, H, visited flags, walker states, tables,
+ * the packed learned network, exchange counters) plus the exchange step,
+ * seed and proposal kind to `path` (host file, overwritten), after
+ * synchronising the stream.  rewl_load needs a context configured with the
+ * same instances, mode and launch-independent layout and with buffers bound;
+ * it restores that state, after which rewl_run continues exactly as the
+ * saved context would have (bit-identical in every mode, since all random
+ * numbers are functions of (seed, walker, attempt count)).  Harvest and trace
+ * targets are not part of the state.  Errors: REWL_EINVAL (file cannot be
+ * opened, read or written), REWL_ECORRUPT (bad magic, short file, or a
+ * fingerprint of the configuration that differs from this context's). */
+rewl_status rewl_save(rewl_ctx *ctx, const char *path);
+rewl_status rewl_load(rewl_ctx *ctx, const char *path);
 
 /* Totals over all walkers of the context (synchronising). */
 rewl_status rewl_total_attempts(rewl_ctx *ctx, uint64_t *attempts, uint64_t *accepts);

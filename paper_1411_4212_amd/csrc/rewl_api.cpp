@@ -104,6 +104,9 @@ struct rewl_ctx {
            off_init = 0;
     // CONTROL layout
     size_t off_ictl = 0, off_xatt = 0, off_xacc = 0;
+    size_t off_pctl = 0, off_parr = 0, off_prnd = 0, off_pslots = 0;
+    uint32_t p_cap = 0;
+    int32_t last_grid = 0;
     int32_t n_walkers = 0, n_xstat = 0;
     int64_t total_bins = 0, total_spins = 0;
     int32_t lds_spins_bytes = 0, lds_bins = 0;
@@ -159,6 +162,12 @@ KArgs make_args(rewl_ctx *c)
     a.ictl = (InstControl *)(Cb + c->off_ictl);
     a.xatt = (unsigned long long *)(Cb + c->off_xatt);
     a.xacc = (unsigned long long *)(Cb + c->off_xacc);
+    a.pctl = (PersistCtl *)(Cb + c->off_pctl);
+    a.p_arrive = (uint32_t *)(Cb + c->off_parr);
+    a.p_rounds = (uint32_t *)(Cb + c->off_prnd);
+    a.p_slots = (unsigned long long *)(Cb + c->off_pslots);
+    a.p_mask = c->p_cap - 1u;
+    a.p_max_rounds = 0;
     a.trace = c->trace;
     a.trace_cap = c->trace_cap;
     a.t = c->t;
@@ -417,6 +426,18 @@ rewl_status finalize(rewl_ctx *c)
     oc = align256(oc + sizeof(unsigned long long) * (size_t)c->n_xstat);
     c->off_xacc = oc;
     oc = align256(oc + sizeof(unsigned long long) * (size_t)c->n_xstat);
+    // persistent-kernel queue: capacity a power of two above every walker
+    // plus every wavefront that may hold a ticket
+    c->p_cap = 256;
+    while (c->p_cap < 2u * (uint32_t)c->n_walkers + 256u) c->p_cap <<= 1;
+    c->off_pctl = oc;
+    oc = align256(oc + sizeof(PersistCtl));
+    c->off_parr = oc;
+    oc = align256(oc + sizeof(uint32_t) * c->inst.size());
+    c->off_prnd = oc;
+    oc = align256(oc + sizeof(uint32_t) * c->inst.size());
+    c->off_pslots = oc;
+    oc = align256(oc + sizeof(unsigned long long) * (size_t)c->p_cap);
     c->sizes[REWL_BUF_CONTROL] = oc;
     return REWL_OK;
 }
@@ -662,6 +683,44 @@ rewl_status rewl_run(rewl_ctx *ctx, int64_t n_segments)
     return REWL_OK;
 }
 
+rewl_status rewl_run_persistent(rewl_ctx *ctx, int64_t max_rounds, int32_t max_blocks, int32_t *grid_out)
+{
+    if (!ctx) return fail(REWL_EINVAL, "null context");
+    if (ctx->stage < 3) return fail(REWL_ESTATE, "initialise walkers first");
+    if (max_rounds < 0 || max_blocks < 0) return fail(REWL_EINVAL, "negative round or block count");
+    if (ctx->mode == REWL_MODE_FP64_DET || ctx->fast_q <= 0)
+        return fail(REWL_EUNSUPPORTED, "the persistent kernel needs FP64 or FP32_DE mode on bcc lattices");
+    if ((double)max_rounds * (double)ctx->n_walkers + 2.0 * ctx->p_cap >= 2147483648.0)
+        return fail(REWL_ERANGE, "too many rounds for one persistent launch; split the call");
+    if (max_rounds == 0) {
+        if (grid_out) *grid_out = 0;
+        return REWL_OK;
+    }
+    int n_cu = 0;
+    HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    KArgs a = make_args(ctx);
+    a.p_max_rounds = (int32_t)max_rounds;
+    // a legitimate wait lasts at most one segment of another walker plus an
+    // exchange: about seg_len trial moves of at most ~10 us each
+    int64_t seg_max = 1;
+    for (auto &d : ctx->idesc) seg_max = std::max<int64_t>(seg_max, d.seg_len);
+    a.p_spin_limit = (uint64_t)std::min<int64_t>(std::max<int64_t>(512 * seg_max, int64_t(1) << 22), int64_t(1) << 32);
+    int grid = 0;
+    int rc = launch_persistent(a, ctx->mode, ctx->stream, ctx->lds_per_walker, n_cu, max_blocks, &grid);
+    if (rc) return fail(rc, "persistent kernel launch failed");
+    ctx->last_grid = grid;
+    if (grid_out) *grid_out = grid;
+    rewl_status st = sync_check(ctx);
+    if (st) return st;
+    PersistCtl pc{};
+    HIP_TRY(hipMemcpy(&pc, (unsigned char *)ctx->buf[REWL_BUF_CONTROL] + ctx->off_pctl, sizeof pc,
+                      hipMemcpyDeviceToHost));
+    if (pc.error) return fail(REWL_EDEVICE, "persistent kernel: a bounded wait ran out");
+    if (!pc.all_done) return fail(REWL_EDEVICE, "persistent kernel ended before every instance stopped");
+    ctx->t += max_rounds;
+    return REWL_OK;
+}
+
 rewl_status rewl_set_launch(rewl_ctx *ctx, int32_t walkers_per_block, int32_t residency)
 {
     if (!ctx) return fail(REWL_EINVAL, "null context");
@@ -809,6 +868,26 @@ rewl_status rewl_read_visited(rewl_ctx *ctx, int32_t inst, int32_t walker, uint8
     return read_bins(ctx, inst, walker, REWL_BUF_VISITED, 1, out, cap, n_out);
 }
 
+rewl_status rewl_write_lng(rewl_ctx *ctx, int32_t inst, int32_t walker, const double *lng,
+                           const uint8_t *visited, int32_t cap)
+{
+    int gw;
+    rewl_status st = check_walker(ctx, inst, walker, &gw);
+    if (st) return st;
+    if (!lng || cap < 0) return fail(REWL_EINVAL, "bad input");
+    st = sync_check(ctx);
+    if (st) return st;
+    const WalkerDesc &wd = ctx->wdesc[gw];
+    const int32_t n = std::min(wd.hi - wd.lo, cap);
+    for (int32_t j = 0; j < n; ++j)
+        if (!std::isfinite(lng[j])) return fail(REWL_EINVAL, "non-finite ln g");
+    std::vector<uint8_t> vis(n, 1);
+    if (visited) vis.assign(visited, visited + n);
+    HIP_TRY(hipMemcpy((double *)ctx->buf[REWL_BUF_LNG] + wd.bin_off, lng, sizeof(double) * n, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy((uint8_t *)ctx->buf[REWL_BUF_VISITED] + wd.bin_off, vis.data(), n, hipMemcpyHostToDevice));
+    return REWL_OK;
+}
+
 rewl_status rewl_read_walker_state(rewl_ctx *ctx, int32_t inst, int32_t walker, rewl_walker_state *out)
 {
     int gw;
@@ -907,6 +986,133 @@ rewl_status rewl_total_attempts(rewl_ctx *ctx, uint64_t *attempts, uint64_t *acc
     }
     *attempts = at;
     *accepts = ac;
+    return REWL_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- checkpoints
+
+namespace {
+
+struct CkptHeader {
+    char magic[8];
+    uint32_t version;
+    int32_t mode;
+    uint64_t fingerprint;
+    uint32_t seed;
+    int32_t proposal;
+    int64_t t;
+    uint64_t sizes[REWL_NBUF];
+};
+constexpr char kCkptMagic[8] = {'R', 'E', 'W', 'L', 'C', 'K', 'P', '1'};
+
+uint64_t fnv1a(uint64_t h, const void *p, size_t n)
+{
+    const unsigned char *b = (const unsigned char *)p;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+// Everything that fixes the meaning of the device buffers: mode, buffer
+// sizes and the host copies of the instance, walker and lattice tables.
+uint64_t fingerprint(const rewl_ctx *c)
+{
+    uint64_t h = 14695981039346656037ull;
+    h = fnv1a(h, &c->mode, sizeof c->mode);
+    h = fnv1a(h, c->sizes, sizeof c->sizes);
+    h = fnv1a(h, c->idesc.data(), c->idesc.size() * sizeof(InstDesc));
+    h = fnv1a(h, c->wdesc.data(), c->wdesc.size() * sizeof(WalkerDesc));
+    h = fnv1a(h, c->slots.data(), c->slots.size() * sizeof(BccSlot));
+    h = fnv1a(h, c->tdeg.data(), c->tdeg.size() * sizeof(int32_t));
+    h = fnv1a(h, c->tnbr.data(), c->tnbr.size() * sizeof(int32_t));
+    h = fnv1a(h, c->tJ.data(), c->tJ.size() * sizeof(double));
+    return h;
+}
+
+constexpr size_t kCkptChunk = size_t(64) << 20;
+
+struct FileCloser {
+    FILE *f;
+    ~FileCloser()
+    {
+        if (f) fclose(f);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+rewl_status rewl_save(rewl_ctx *ctx, const char *path)
+{
+    if (!ctx || !path) return fail(REWL_EINVAL, "null argument");
+    if (ctx->stage < 3) return fail(REWL_ESTATE, "initialise walkers first");
+    rewl_status st = sync_check(ctx);
+    if (st) return st;
+    CkptHeader hd{};
+    memcpy(hd.magic, kCkptMagic, 8);
+    hd.version = 1;
+    hd.mode = ctx->mode;
+    hd.fingerprint = fingerprint(ctx);
+    hd.seed = ctx->seed;
+    hd.proposal = ctx->proposal;
+    hd.t = ctx->t;
+    for (int b = 0; b < REWL_NBUF; ++b) hd.sizes[b] = ctx->sizes[b];
+    FileCloser fc{fopen(path, "wb")};
+    if (!fc.f) return fail(REWL_EINVAL, std::string("cannot open checkpoint for writing: ") + path);
+    if (fwrite(&hd, sizeof hd, 1, fc.f) != 1) return fail(REWL_EINVAL, "checkpoint write failed");
+    std::vector<unsigned char> tmp;
+    for (int b = 0; b < REWL_NBUF; ++b) {
+        for (size_t off = 0; off < ctx->sizes[b]; off += kCkptChunk) {
+            const size_t n = std::min(kCkptChunk, ctx->sizes[b] - off);
+            tmp.resize(n);
+            HIP_TRY(hipMemcpy(tmp.data(), (unsigned char *)ctx->buf[b] + off, n, hipMemcpyDeviceToHost));
+            if (fwrite(tmp.data(), 1, n, fc.f) != n) return fail(REWL_EINVAL, "checkpoint write failed");
+        }
+    }
+    if (fflush(fc.f) != 0) return fail(REWL_EINVAL, "checkpoint write failed");
+    return REWL_OK;
+}
+
+rewl_status rewl_load(rewl_ctx *ctx, const char *path)
+{
+    if (!ctx || !path) return fail(REWL_EINVAL, "null argument");
+    if (ctx->stage < 2) return fail(REWL_ESTATE, "bind buffers before loading a checkpoint");
+    rewl_status st = sync_check(ctx);
+    if (st) return st;
+    FileCloser fc{fopen(path, "rb")};
+    if (!fc.f) return fail(REWL_EINVAL, std::string("cannot open checkpoint: ") + path);
+    CkptHeader hd{};
+    if (fread(&hd, sizeof hd, 1, fc.f) != 1) return fail(REWL_ECORRUPT, "checkpoint too short");
+    if (memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != 1)
+        return fail(REWL_ECORRUPT, "not a checkpoint of this library version");
+    if (hd.mode != ctx->mode) return fail(REWL_ECORRUPT, "checkpoint was written in another arithmetic mode");
+    for (int b = 0; b < REWL_NBUF; ++b)
+        if (hd.sizes[b] != ctx->sizes[b]) return fail(REWL_ECORRUPT, "checkpoint buffer sizes differ from this context");
+    if (hd.fingerprint != fingerprint(ctx))
+        return fail(REWL_ECORRUPT, "checkpoint belongs to a different configuration");
+    if (hd.proposal != 0 && hd.proposal != 1) return fail(REWL_ECORRUPT, "bad proposal kind in checkpoint");
+    // read everything before touching the device, so that a short file
+    // leaves the context as it was
+    std::vector<std::vector<unsigned char>> data(REWL_NBUF);
+    for (int b = 0; b < REWL_NBUF; ++b) {
+        data[b].resize(ctx->sizes[b]);
+        if (ctx->sizes[b] && fread(data[b].data(), 1, ctx->sizes[b], fc.f) != ctx->sizes[b])
+            return fail(REWL_ECORRUPT, "checkpoint truncated");
+    }
+    unsigned char extra;
+    if (fread(&extra, 1, 1, fc.f) != 0) return fail(REWL_ECORRUPT, "trailing bytes in checkpoint");
+    for (int b = 0; b < REWL_NBUF; ++b)
+        if (ctx->sizes[b])
+            HIP_TRY(hipMemcpy(ctx->buf[b], data[b].data(), ctx->sizes[b], hipMemcpyHostToDevice));
+    ctx->seed = hd.seed;
+    ctx->proposal = hd.proposal;
+    ctx->t = hd.t;
+    ctx->stage = 3;
     return REWL_OK;
 }
 

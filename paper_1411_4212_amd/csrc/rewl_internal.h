@@ -70,6 +70,18 @@ struct InstControl {
     int32_t pad;
 };
 
+// Work queue of the persistent kernel (CONTROL buffer).  A slot holds
+// (sequence << 32 | walker); slot j starts with sequence j (empty).  A
+// producer of ticket p waits for sequence p, writes (p + 1, walker); the
+// consumer of ticket p waits for p + 1 and leaves p + capacity.
+struct PersistCtl {
+    uint32_t head, tail;       // consumer / producer tickets
+    uint32_t finished;         // instances that have stopped
+    uint32_t all_done;         // set once every instance has stopped
+    uint32_t error;            // a bounded wait ran out
+    uint32_t pad[11];
+};
+
 struct KArgs {
     void *spins;
     WalkerState *state;
@@ -102,6 +114,14 @@ struct KArgs {
     const void *mlp;           // packed learned-proposal network (nullptr: uniform proposal)
     float *harvest;            // training records [walker][harvest_cap][8] (nullptr: off)
     int64_t harvest_cap;
+    // persistent kernel
+    PersistCtl *pctl;
+    uint32_t *p_arrive;        // per instance: walker arrivals in this launch
+    uint32_t *p_rounds;        // per instance: rounds completed in this launch
+    unsigned long long *p_slots;
+    uint32_t p_mask;           // queue capacity - 1 (power of two >= walkers)
+    int32_t p_max_rounds;
+    uint64_t p_spin_limit;     // polls before a wait gives up
 };
 
 constexpr int kWave = 64;
@@ -115,5 +135,9 @@ int launch_mlp_pack(const float *dev_params, void *dev_packed, hipStream_t s);
 int launch_init(const KArgs &a, int mode, hipStream_t s, size_t lds_per_walker);
 int launch_sweep(const KArgs &a, int mode, hipStream_t s, size_t lds_per_walker);
 int launch_exchange(const KArgs &a, hipStream_t s);
+// Persistent form: every instance runs up to a.p_max_rounds rounds
+// (segment + exchange) in one launch; `n_cu` compute units.
+int launch_persistent(const KArgs &a, int mode, hipStream_t s, size_t lds_per_walker, int n_cu,
+                      int max_blocks, int *grid_out);
 
 }  // namespace rewl

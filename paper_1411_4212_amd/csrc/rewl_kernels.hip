@@ -547,75 +547,86 @@ __global__ void __launch_bounds__(256) sweep_kernel(KArgs a)
 }
 
 // ------------------------------------------------------------------ exchange
-// One replica-exchange step for every instance not yet done: window pairs
-// (k, k+1) with k of the parity of the step counter; the m walkers of window
-// k are paired with those of window k+1 by a Fisher-Yates permutation; a pair
-// may swap only if each energy lies in the other's window on a bin that
-// walker has visited; the swap moves configuration, energy and bin.  Then
-// the instance's done flag is recomputed.
-__global__ void __launch_bounds__(64) exchange_kernel(KArgs a)
+// One replica-exchange step of instance ii at step t, by one wavefront:
+// window pairs (k, k+1) with k of the parity of t; the m walkers of window k
+// are paired with those of window k+1 by a Fisher-Yates permutation (lane r
+// holds entry r); a pair may swap only if each energy lies in the other's
+// window on a bin that walker has visited; the swap moves configuration,
+// energy and bin.  Lanes r < m decide the m pairs of a window pair at once
+// (they touch disjoint walkers).  Then the instance's done flag is
+// recomputed.
+__device__ void exchange_instance(const KArgs &a, int ii, uint64_t t)
 {
-    __shared__ int perm_all[kWave][REWL_MAX_WALKERS_PER_WINDOW];
-    __shared__ int all_done;
-    const int ii = blockIdx.x;
-    if (ii >= a.n_inst) return;
-    if (a.ictl[ii].done) return;
+    const int lane = __lane_id();
     const InstDesc I = a.inst[ii];
-    const int tid = threadIdx.x;
-    const uint64_t t = (uint64_t)a.t;
     const int m = I.m;
-    int *perm = perm_all[tid];
-    for (int k = (int)(t & 1u) + 2 * tid; k + 1 < I.h; k += 2 * kWave) {
-        for (int r = 0; r < m; ++r) perm[r] = r;
+    for (int k = (int)(t & 1u); k + 1 < I.h; k += 2) {
+        int pr = lane;
         for (int i = m - 1; i >= 1; --i) {
             const U4 rr = draw(a.seed, (uint32_t)ii, t, ((uint32_t)k << 16) | (uint32_t)i, TAG_PERM);
             const int j = (int)__umulhi(rr.x, (uint32_t)(i + 1));
-            const int tmp = perm[i];
-            perm[i] = perm[j];
-            perm[j] = tmp;
+            const int pi = __shfl(pr, i, kWave), pj = __shfl(pr, j, kWave);
+            pr = (lane == i) ? pj : ((lane == j) ? pi : pr);
         }
-        for (int r = 0; r < m; ++r) {
+        bool swapped = false;
+        if (lane < m) {
+            const int r = lane;
             const int wa = I.walker_base + k * m + r;
-            const int wb = I.walker_base + (k + 1) * m + perm[r];
+            const int wb = I.walker_base + (k + 1) * m + pr;
             const WalkerDesc da = a.wdesc[wa], db = a.wdesc[wb];
             WalkerState *sa = a.state + wa;
             WalkerState *sb = a.state + wb;
-            a.xatt[I.xstat_off + k] += 1ull;
             const double Ea = sa->E, Eb = sb->E;
             const double xa = (Ea - I.Emin) * I.inv_de;
             const double xb = (Eb - I.Emin) * I.inv_de;
-            if (!(xa >= (double)db.lo && xa < (double)db.hi)) continue;
-            if (!(xb >= (double)da.lo && xb < (double)da.hi)) continue;
-            const int ba = (int)floor(xa), bbn = (int)floor(xb);
-            if (!a.vis[db.bin_off + (ba - db.lo)] || !a.vis[da.bin_off + (bbn - da.lo)]) continue;
-            const U4 rr = draw(a.seed, (uint32_t)ii, t, ((uint32_t)k << 16) | (uint32_t)r, TAG_EXCH);
-            const double u = u53(rr.x, rr.y);
+            bool ok = (xa >= (double)db.lo && xa < (double)db.hi) && (xb >= (double)da.lo && xb < (double)da.hi);
             const int bina = sa->bin, binb = sb->bin;
-            // stored bins (a resync may have clamped them) must lie in the
-            // other window as well
-            if (bina < db.lo || bina >= db.hi || binb < da.lo || binb >= da.hi) continue;
-            const double lga_a = a.lng[da.bin_off + (bina - da.lo)];
-            const double lga_b = a.lng[da.bin_off + (binb - da.lo)];
-            const double lgb_b = a.lng[db.bin_off + (binb - db.lo)];
-            const double lgb_a = a.lng[db.bin_off + (bina - db.lo)];
-            const double lr = (lga_a - lga_b) + (lgb_b - lgb_a);
-            if (!((lr >= 0.0) || (u < exp_det(lr)))) continue;
-            a.xacc[I.xstat_off + k] += 1ull;
-            const int tc = sa->cfg;
-            sa->cfg = sb->cfg;
-            sb->cfg = tc;
-            sa->E = Eb;
-            sb->E = Ea;
-            sa->bin = binb;
-            sb->bin = bina;
+            if (ok) {
+                const int ba = (int)floor(xa), bbn = (int)floor(xb);
+                ok = a.vis[db.bin_off + (ba - db.lo)] && a.vis[da.bin_off + (bbn - da.lo)];
+                // stored bins (a resync may have clamped them) must lie in
+                // the other window as well
+                ok = ok && !(bina < db.lo || bina >= db.hi || binb < da.lo || binb >= da.hi);
+            }
+            if (ok) {
+                const U4 rr = draw(a.seed, (uint32_t)ii, t, ((uint32_t)k << 16) | (uint32_t)r, TAG_EXCH);
+                const double u = u53(rr.x, rr.y);
+                const double lga_a = a.lng[da.bin_off + (bina - da.lo)];
+                const double lga_b = a.lng[da.bin_off + (binb - da.lo)];
+                const double lgb_b = a.lng[db.bin_off + (binb - db.lo)];
+                const double lgb_a = a.lng[db.bin_off + (bina - db.lo)];
+                const double lr = (lga_a - lga_b) + (lgb_b - lgb_a);
+                if ((lr >= 0.0) || (u < exp_det(lr))) {
+                    swapped = true;
+                    const int tc = sa->cfg;
+                    sa->cfg = sb->cfg;
+                    sb->cfg = tc;
+                    sa->E = Eb;
+                    sb->E = Ea;
+                    sa->bin = binb;
+                    sb->bin = bina;
+                }
+            }
+        }
+        const unsigned long long nacc = (unsigned long long)__popcll(__builtin_amdgcn_ballot_w64(swapped));
+        if (lane == 0) {
+            __hip_atomic_fetch_add(a.xatt + I.xstat_off + k, (unsigned long long)m, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(a.xacc + I.xstat_off + k, nacc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
-    if (tid == 0) all_done = 1;
-    __syncthreads();
-    for (int w = tid; w < I.n_walkers; w += kWave)
-        if (!a.state[I.walker_base + w].done) all_done = 0;
-    __syncthreads();
-    if (tid == 0 && all_done) a.ictl[ii].done = 1;
+    bool running = false;
+    for (int w = lane; w < I.n_walkers; w += kWave) running |= (a.state[I.walker_base + w].done == 0);
+    const bool all_done = __builtin_amdgcn_ballot_w64(running) == 0ull;
+    if (lane == 0 && all_done) a.ictl[ii].done = 1;
+}
+
+__global__ void __launch_bounds__(64) exchange_kernel(KArgs a)
+{
+    const int ii = blockIdx.x;
+    if (ii >= a.n_inst) return;
+    if (a.ictl[ii].done) return;
+    exchange_instance(a, ii, (uint64_t)a.t);
 }
 
 
@@ -688,16 +699,13 @@ struct FastLat {
     uint32_t M, Hm;          // SWAR masks: field bits below the top bit / top bits
 };
 
+// One segment of walker w by the calling wavefront, in LDS slot `wave`.
 template <int MODE, int Q, bool POW2, bool LDS_SPINS, bool LEARNED>
-__global__ void __launch_bounds__(256) sweep_fast_kernel(KArgs a)
+__device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const int wave, unsigned char *lds_raw)
 {
     using T = typename Spin<MODE>::T;
     using V = typename Spin<MODE>::V;
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = __lane_id();
-    const int w = blockIdx.x * a.walkers_per_block + wave;
-    if (w >= a.n_walkers) return;
     const WalkerDesc wd = a.wdesc[w];
     if (a.ictl[wd.inst].done) return;
     const InstDesc I = a.inst[wd.inst];
@@ -1065,6 +1073,212 @@ __global__ void __launch_bounds__(256) sweep_fast_kernel(KArgs a)
     }
 }
 
+template <int MODE, int Q, bool POW2, bool LDS_SPINS, bool LEARNED>
+__global__ void __launch_bounds__(256) sweep_fast_kernel(KArgs a)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int w = blockIdx.x * a.walkers_per_block + wave;
+    if (w >= a.n_walkers) return;
+    fast_segment<MODE, Q, POW2, LDS_SPINS, LEARNED>(a, w, wave, lds_raw);
+}
+
+// ------------------------------------------------------------------ persistent
+// Every instance runs up to p_max_rounds rounds (a segment of each of its
+// walkers, then its exchange step) in one launch, independently of the
+// other instances.  Wavefronts take walkers from a bounded multi-producer
+// multi-consumer queue; the last walker of an instance to finish a round
+// runs that instance's exchange and queues the instance's walkers for the
+// next round (or marks the instance stopped).  A wavefront waits only while
+// the queue is empty, and the walkers it waits for are held by running
+// wavefronts, so no launch shape can deadlock.  Every wait is bounded: past
+// the limit the wavefront raises `error`, sets all_done and leaves, so the
+// grid always drains (the limit, in polls of at least ~50 ns, is set by the
+// host well above the longest segment).  Synchronisation is release/acquire at agent scope
+// (the L2 caches of the chip are not coherent with each other).  Every
+// branch and loop of the persistent loop is wave-uniform: values that steer
+// it are broadcast with readfirstlane, since the segment's wavefront-level
+// operations (DPP sums, readlane, ballots) need all 64 lanes active.
+
+__device__ __forceinline__ uint32_t ld_acq(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long ld_acq64(const unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rel64(unsigned long long *p, unsigned long long v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rel(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t add_acqrel(uint32_t *p, uint32_t v)
+{
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void persist_abort(const KArgs &a)
+{
+    st_rel(&a.pctl->error, 1u);
+    st_rel(&a.pctl->all_done, 1u);
+}
+
+// The queue operations below are called by the whole wavefront and keep
+// every branch and loop wave-uniform (values broadcast with readfirstlane,
+// readiness of several slots combined with a ballot).
+
+// Next walker, or -1 when all is done.
+__device__ int persist_pop(const KArgs &a)
+{
+    const int lane = __lane_id();
+    uint32_t t = 0;
+    if (lane == 0) t = add_acqrel(&a.pctl->head, 1u);
+    t = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
+    unsigned long long *slot = a.p_slots + (t & a.p_mask);
+    for (uint64_t it = 0;; ++it) {
+        const unsigned long long v = ld_acq64(slot);
+        const uint32_t seq = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+        if (seq == t + 1u) {
+            const int w = __builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+            if (lane == 0) st_rel64(slot, (unsigned long long)(t + a.p_mask + 1u) << 32);
+            return w;
+        }
+        const uint32_t done = (uint32_t)__builtin_amdgcn_readfirstlane((int)ld_acq(&a.pctl->all_done));
+        if (done) return -1;
+        if (it >= a.p_spin_limit) {
+            if (lane == 0) persist_abort(a);
+            return -1;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
+
+// Queue walkers base .. base + n - 1.
+__device__ void persist_push_range(const KArgs &a, int base, int n)
+{
+    const int lane = __lane_id();
+    uint32_t p0 = 0;
+    if (lane == 0) p0 = __hip_atomic_fetch_add(&a.pctl->tail, (uint32_t)n, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    p0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)p0);
+    for (int c0 = 0; c0 < n; c0 += kWave) {
+        const bool active = c0 + lane < n;
+        const uint32_t p = p0 + (uint32_t)(c0 + lane);
+        unsigned long long *slot = a.p_slots + (p & a.p_mask);
+        bool ready = false;
+        for (uint64_t it = 0;; ++it) {
+            const bool ok = !active || (uint32_t)(ld_acq64(slot) >> 32) == p;
+            if (__builtin_amdgcn_ballot_w64(!ok) == 0ull) {
+                ready = true;
+                break;
+            }
+            const uint32_t done = (uint32_t)__builtin_amdgcn_readfirstlane((int)ld_acq(&a.pctl->all_done));
+            if (done || it >= a.p_spin_limit) break;
+            __builtin_amdgcn_s_sleep(2);
+        }
+        if (!ready) {
+            if (lane == 0) persist_abort(a);
+            return;
+        }
+        if (active) st_rel64(slot, ((unsigned long long)(p + 1u) << 32) | (uint32_t)(base + c0 + lane));
+    }
+}
+
+template <int MODE, int Q, bool POW2, bool LDS_SPINS, bool LEARNED>
+__global__ void __launch_bounds__(256) persistent_kernel(KArgs a)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = __lane_id();
+    for (;;) {
+        const int w = persist_pop(a);
+        if (w < 0) break;
+        if (w >= a.n_walkers) {
+            if (lane == 0) persist_abort(a);
+            break;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        fast_segment<MODE, Q, POW2, LDS_SPINS, LEARNED>(a, w, wave, lds_raw);
+        wave_sync();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // every control value wave-uniform (loads land in vector registers)
+        const int ii = __builtin_amdgcn_readfirstlane(a.wdesc[w].inst);
+        const int nw = __builtin_amdgcn_readfirstlane(a.inst[ii].n_walkers);
+        const int wbase = __builtin_amdgcn_readfirstlane(a.inst[ii].walker_base);
+        // arrivals are counted without reset: the nw-th arrival of a round
+        // leaves a multiple of nw
+        uint32_t prev = 0;
+        if (lane == 0) prev = add_acqrel(a.p_arrive + ii, 1u);
+        prev = (uint32_t)__builtin_amdgcn_readfirstlane((int)prev);
+        if ((prev + 1u) % (uint32_t)nw != 0u) continue;
+        // last walker of instance ii in this round: exchange, then the next round
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        uint32_t r = 0;
+        if (lane == 0) r = add_acqrel(a.p_rounds + ii, 1u);
+        r = (uint32_t)__builtin_amdgcn_readfirstlane((int)r);
+        exchange_instance(a, ii, (uint64_t)a.t + r);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const int done_i = __builtin_amdgcn_readfirstlane(a.ictl[ii].done);
+        const bool stop = done_i != 0 || (int32_t)(r + 1u) >= a.p_max_rounds;
+        if (!stop) {
+            persist_push_range(a, wbase, nw);
+        } else {
+            uint32_t f = 0;
+            if (lane == 0) f = add_acqrel(&a.pctl->finished, 1u);
+            f = (uint32_t)__builtin_amdgcn_readfirstlane((int)f);
+            if (f + 1u == (uint32_t)a.n_inst && lane == 0) st_rel(&a.pctl->all_done, 1u);
+        }
+    }
+}
+
+// Queue set-up for a persistent launch (one block): walkers of instances
+// not yet done are queued, done instances count as finished.
+__global__ void __launch_bounds__(256) persistent_prep_kernel(KArgs a)
+{
+    __shared__ int n_active;
+    __shared__ int n_done;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        int q = 0, d = 0;
+        for (int i = 0; i < a.n_inst; ++i) {
+            if (a.ictl[i].done) {
+                ++d;
+            } else {
+                q += a.inst[i].n_walkers;
+            }
+        }
+        n_active = q;
+        n_done = d;
+    }
+    __syncthreads();
+    for (int i = tid; i < a.n_inst; i += blockDim.x) {
+        a.p_arrive[i] = 0u;
+        a.p_rounds[i] = 0u;
+    }
+    // queued walkers in instance order
+    if (tid == 0) {
+        int q = 0;
+        for (int i = 0; i < a.n_inst; ++i) {
+            if (a.ictl[i].done) continue;
+            const int b = a.inst[i].walker_base;
+            for (int w = 0; w < a.inst[i].n_walkers; ++w, ++q)
+                a.p_slots[q] = ((unsigned long long)(q + 1) << 32) | (uint32_t)(b + w);
+        }
+    }
+    for (uint32_t j = (uint32_t)n_active + tid; j <= a.p_mask; j += blockDim.x)
+        a.p_slots[j] = (unsigned long long)j << 32;
+    if (tid == 0) {
+        a.pctl->head = 0u;
+        a.pctl->tail = (uint32_t)n_active;
+        a.pctl->finished = (uint32_t)n_done;
+        a.pctl->all_done = (n_done == a.n_inst || a.p_max_rounds <= 0) ? 1u : 0u;
+        a.pctl->error = 0u;
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 static size_t lds_bytes(const KArgs &a, size_t per_walker)
 {
@@ -1141,6 +1355,53 @@ int launch_exchange(const KArgs &a, hipStream_t s)
 {
     hipLaunchKernelGGL(exchange_kernel, dim3(a.n_inst), dim3(kWave), 0, s, a);
     return hipGetLastError() == hipSuccess ? REWL_OK : REWL_EDEVICE;
+}
+
+template <int MODE, int Q, bool POW2, bool LDS_SPINS, bool LEARNED>
+static int launch_persist_t(const KArgs &a, hipStream_t s, size_t lds, int n_cu, int max_blocks, int *grid_out)
+{
+    const int wpb = a.walkers_per_block;
+    const auto kern = persistent_kernel<MODE, Q, POW2, LDS_SPINS, LEARNED>;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kWave * wpb, lds) != hipSuccess || per_cu < 1)
+        return REWL_EUNSUPPORTED;
+    const int need = (a.n_walkers + wpb - 1) / wpb;
+    int grid = std::max(1, std::min(need, per_cu * n_cu));
+    if (max_blocks > 0) grid = std::min(grid, max_blocks);
+    *grid_out = grid;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kWave * wpb), lds, s, a);
+    return hipGetLastError() == hipSuccess ? REWL_OK : REWL_EDEVICE;
+}
+
+int launch_persistent(const KArgs &a, int mode, hipStream_t s, size_t per_walker, int n_cu, int max_blocks,
+                      int *grid_out)
+{
+    if (a.fast_q <= 0 || mode == M_DET) return REWL_EUNSUPPORTED;
+    hipLaunchKernelGGL(persistent_prep_kernel, dim3(1), dim3(256), 0, s, a);
+    if (hipGetLastError() != hipSuccess) return REWL_EDEVICE;
+    const size_t lds = lds_bytes(a, per_walker);
+#define REWL_PERS(M, Qv, P2)                                                                              \
+    do {                                                                                                  \
+        if (a.mlp && M == M_F32)                                                                          \
+            return a.spins_in_lds ? launch_persist_t<M_F32, Qv, P2, true, true>(a, s, lds, n_cu, max_blocks, grid_out)   \
+                                  : launch_persist_t<M_F32, Qv, P2, false, true>(a, s, lds, n_cu, max_blocks, grid_out); \
+        return a.spins_in_lds ? launch_persist_t<M, Qv, P2, true, false>(a, s, lds, n_cu, max_blocks, grid_out)          \
+                              : launch_persist_t<M, Qv, P2, false, false>(a, s, lds, n_cu, max_blocks, grid_out);        \
+    } while (0)
+#define REWL_PERS_Q(M, P2)                  \
+    switch (a.fast_q) {                     \
+    case 1: REWL_PERS(M, 1, P2);            \
+    case 4: REWL_PERS(M, 4, P2);            \
+    case 8: REWL_PERS(M, 8, P2);            \
+    default: return REWL_EINVAL;            \
+    }
+    if (mode == M_F32) {
+        if (a.all_pow2) { REWL_PERS_Q(M_F32, true) } else { REWL_PERS_Q(M_F32, false) }
+    } else {
+        if (a.all_pow2) { REWL_PERS_Q(M_F64, true) } else { REWL_PERS_Q(M_F64, false) }
+    }
+#undef REWL_PERS_Q
+#undef REWL_PERS
 }
 
 }  // namespace rewl

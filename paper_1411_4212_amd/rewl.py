@@ -72,6 +72,10 @@ _SIGS = {
     "rewl_read_visited": [_vp, _i32, _i32, _P(C.c_uint8), _i32, _P(_i32)],
     "rewl_read_walker_state": [_vp, _i32, _i32, _P(rewl_walker_state)],
     "rewl_read_config": [_vp, _i32, _i32, _P(_dbl), _i64],
+    "rewl_write_lng": [_vp, _i32, _i32, _P(_dbl), _P(C.c_uint8), _i32],
+    "rewl_save": [_vp, C.c_char_p],
+    "rewl_run_persistent": [_vp, _i64, _i32, _P(_i32)],
+    "rewl_load": [_vp, C.c_char_p],
     "rewl_read_window": [_vp, _i32, _i32, _P(_i32), _P(_i32)],
     "rewl_read_exchange_stats": [_vp, _i32, _P(_u64), _P(_u64), _i32],
     "rewl_read_step": [_vp, _P(_i64)],
@@ -220,6 +224,29 @@ def rewl_read_walker_state(ctx, inst, walker):
     st = rewl_walker_state()
     _call("rewl_read_walker_state", ctx, inst, walker, C.byref(st))
     return {f: getattr(st, f) for f, _ in rewl_walker_state._fields_}
+
+
+def rewl_write_lng(ctx, inst, walker, lng, visited=None):
+    lng = np.ascontiguousarray(lng, dtype=np.float64)
+    if visited is None:
+        _call("rewl_write_lng", ctx, inst, walker, _dp(lng), None, len(lng))
+    else:
+        v = np.ascontiguousarray(visited, dtype=np.uint8)
+        _call("rewl_write_lng", ctx, inst, walker, _dp(lng), v.ctypes.data_as(_P(C.c_uint8)), len(lng))
+
+
+def rewl_run_persistent(ctx, max_rounds, max_blocks=0):
+    g = _i32(0)
+    _call("rewl_run_persistent", ctx, max_rounds, max_blocks, C.byref(g))
+    return g.value
+
+
+def rewl_save(ctx, path):
+    _call("rewl_save", ctx, os.fsencode(path))
+
+
+def rewl_load(ctx, path):
+    _call("rewl_load", ctx, os.fsencode(path))
 
 
 def rewl_read_config(ctx, inst, config, N):
@@ -415,6 +442,20 @@ class Run:
 
     def walker(self, inst, walker):
         return rewl_read_walker_state(self.ctx, inst, walker)
+
+    def write_lng(self, inst, walker, lng, visited=None):
+        rewl_write_lng(self.ctx, inst, walker, lng, visited)
+
+    def run_persistent(self, max_rounds, max_blocks=0):
+        """All instances advance up to max_rounds rounds in one launch;
+        returns the grid size used."""
+        return rewl_run_persistent(self.ctx, max_rounds, max_blocks)
+
+    def save(self, path):
+        rewl_save(self.ctx, path)
+
+    def load(self, path):
+        rewl_load(self.ctx, path)
 
     def config(self, inst, cfg):
         return rewl_read_config(self.ctx, inst, cfg, self.inst[inst]["N"])

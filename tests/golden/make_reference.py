@@ -4,9 +4,12 @@ the reference of the GPU statistical parity test.
 
 Calls only the CPU oracle.  Usage: python tests/golden/make_reference.py [runs] [threads]
 
-Workload: bcc L=4 (128 spins), J = (1, 0.5), E in [-550, -50) on 40 bins,
-2 windows (o = 0.75) x 8 walkers, flatness 0.8, ln f 1 -> 2^-14, 2e5 moves
-per segment, resync every 100 N moves; run r uses seed 1000 + r.
+Workload: bcc L=4 (128 spins), J = (1, 0.5), E in [-400, -100) on 30 bins
+(the middle of the spectrum, so that every bin is well sampled and the
+run-to-run spread of ln g stays near 0.02-0.05), 2 windows (o = 0.75) x 8
+walkers, flatness 0.8, ln f 1 -> 2^-18, 2e5 moves per segment, resync every
+100 N moves; run r uses seed 1000 + r.  The specific heat of this range
+peaks near T = 2.8.
 Each run's walkers are combined per window and the windows joined where the
 slopes of ln g coincide; the joined ln g is normalised to zero mean.
 """
@@ -21,8 +24,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
-WORKLOAD = dict(lattice=("bcc", 4, [1.0, 0.5]), windows=(-550.0, -50.0, 40, 2, 0.75, 8),
-                schedule=(4, 5, 1.0, 2.0 ** -14, 200000, 12800))
+WORKLOAD = dict(lattice=("bcc", 4, [1.0, 0.5]), windows=(-400.0, -100.0, 30, 2, 0.75, 8),
+                schedule=(4, 5, 1.0, 2.0 ** -18, 200000, 12800))
 OUT = os.path.join(HERE, "ref_parity_L4.json")
 
 
@@ -48,7 +51,7 @@ def one_run(seed, threads):
 
 
 def main():
-    runs = int(sys.argv[1]) if len(sys.argv) > 1 else 128
+    runs = int(sys.argv[1]) if len(sys.argv) > 1 else 256
     threads = int(sys.argv[2]) if len(sys.argv) > 2 else 8
     from oracle.analysis import cv_peak
     Emin, Emax, B = WORKLOAD["windows"][:3]

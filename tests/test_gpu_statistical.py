@@ -21,7 +21,7 @@ from helpers import gpu_from
 
 pytestmark = pytest.mark.gpu
 REF = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "ref_parity_L4.json")
-RUNS = 128
+RUNS = 256
 
 
 def _say(*a):
@@ -61,6 +61,10 @@ def test_statistical_parity_L4(mode):
     delta = dg - dr
     se = np.sqrt(np.nanstd(A, axis=0, ddof=1) ** 2 / RUNS + np.array(ref["std_lng"]) ** 2 / ref["runs"])
     z = np.abs(delta[ok]) / se[ok]
+    np.set_printoptions(precision=3, suppress=True, linewidth=200)
+    _say("delta", delta[ok])
+    _say("z    ", z)
+    _say("se   ", se[ok])
     _say("max|delta| %.4f  max z %.2f" % (np.nanmax(np.abs(delta[ok])), z.max()))
     assert np.nanmax(np.abs(delta[ok])) <= 0.02
     assert z.max() <= 5.0
