@@ -21,6 +21,25 @@ sys.path.insert(0, ROOT)
 LDS_PEAK_GBS = 256 * 128 * 2.4          # 256 CUs x 128 B/clk x 2.4 GHz = 78643 GB/s
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per sweep launch of the benchmark workload, from two rocprofv3
+# --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a
+# plain copy of known size; keyed by the digest of the kernel sources they
+# were taken on (a changed kernel reports null until measured again).
+MEASURED_TRAFFIC = {
+    # profiles/sweep_fast_c2_fp32_counters.md: FETCH 1374.5 KiB x 2.00 + WRITE 2754.5 KiB x 1.00
+    ("aaca17cd26a62054", "fp32_de"): 5636000,
+}
+KERNEL_SOURCES = ["rewl_kernels.hip", "rewl_device.h", "rewl_internal.h", "rewl_mlp_device.h"]
+
+
+def kernel_digest():
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1411_4212_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -61,6 +80,55 @@ def cpu_baseline(cfg, seconds):
                       "%.1f s)" % (segs, W, seg, dt)}
 
 
+def _timed(r, fn, torch):
+    torch.cuda.synchronize()
+    a0, _ = r.total_attempts()
+    t0 = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    a1, _ = r.total_attempts()
+    return (a1 - a0) / dt, dt
+
+
+def extra_measurements(torch, workloads, Run):
+    """The same kernels on workloads that fill the chip (reported beside the
+    headline figure): the 64 uneven instances in the persistent kernel with
+    an autotuned launch shape, and the L=16 eight-shell workload (1024
+    walkers) with the uniform and with the learned proposal."""
+    import numpy as np
+    out = {}
+    cfgs = workloads.batched(64)
+    r = Run([dict(lattice=c["lattice"], windows=c["windows"], schedule=c["schedule"]) for c in cfgs],
+            mode="fp32_de")
+    r.init(cfgs[0]["seed"])
+    trials = r.autotune(segments=1, persistent=True)
+    lc = r.launch()
+    rate, dt = _timed(r, lambda: r.run_persistent(3), torch)
+    out["batched_64_instances"] = {
+        "walkers": r.n_walkers, "attempts_per_s": rate, "seconds": dt, "rounds": 3,
+        "kernel": "persistent_kernel (fp32_de)", "walkers_per_block": lc["walkers_per_block"],
+        "spins_in_lds": lc["spins_in_lds"],
+        "autotune_ms_per_segment": {"%dx%s" % (t["walkers_per_block"], "lds" if t["residency"] == 1 else "hbm"):
+                                    (round(t["ms_per_segment"], 3) if t["status"] == 0 else None) for t in trials}}
+    r.close()
+    log("bench: batched %.3e attempts/s" % rate)
+    c4 = workloads.c4()
+    from paper_1411_4212_amd import learned
+    for kind in ("uniform", "learned"):
+        r = Run([dict(lattice=c4["lattice"], windows=c4["windows"], schedule=c4["schedule"])], mode="fp32_de")
+        r.init(c4["seed"], workloads.init_spins(c4))
+        if kind == "learned":
+            r.set_proposal(learned.init_params(1, torch.device("cuda", 0)))
+        r.run(1)
+        rate, dt = _timed(r, lambda: r.run(2), torch)
+        out["L16_8shell_%s" % kind] = {"walkers": r.n_walkers, "attempts_per_s": rate, "seconds": dt,
+                                       "segments": 2, "proposal": kind}
+        r.close()
+        log("bench: L16 %s %.3e attempts/s" % (kind, rate))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +137,10 @@ def main():
     ap.add_argument("--mode", default="fp32_de", choices=["fp32_de", "fp64", "fp64_det"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the chip-filling workloads reported under 'extra'")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the timed region, copy a 256 MiB buffer 3 times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the REWL hot path here is single-GPU "
@@ -117,6 +189,19 @@ def main():
     per_launch_bytes = bytes_per_attempt(zsum, args.mode) * W * seg
     achieved = per_launch_bytes / avg_sweep_s / 1e9
     log("bench: %.3e attempts/s, sweep %.3f ms avg" % (attempts / wall, avg_sweep_s * 1e3))
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("bench: copy calibration done (3 x 256 MiB)")
+    digest = kernel_digest()
+    traffic = MEASURED_TRAFFIC.get((digest, args.mode))
+
+    extra = None
+    if not args.no_extra:
+        extra = extra_measurements(torch, workloads, Run)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -143,11 +228,13 @@ def main():
                    "mode": args.mode, "walkers": W, "attempts_timed": attempts,
                    "parallelism": "one wavefront per walker, single GPU"},
         "roofline": {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / LDS_PEAK_GBS, "traffic": None,
-                     "kernel": "sweep_kernel<%s>" % args.mode,
+                     "frac": achieved / LDS_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch", "kernel_digest": digest,
+                     "kernel": "sweep_fast_kernel (%s)" % args.mode,
                      "bytes_per_attempt": bytes_per_attempt(zsum, args.mode),
                      "avg_launch_ms": avg_sweep_s * 1e3},
         "cpu_baseline": cpu,
+        "extra": extra,
     }
     print(json.dumps(out), flush=True)
 

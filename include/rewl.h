@@ -178,6 +178,30 @@ rewl_status rewl_set_launch(rewl_ctx *ctx, int32_t walkers_per_block, int32_t re
 rewl_status rewl_get_launch(rewl_ctx *ctx, int32_t *walkers_per_block, int32_t *spins_in_lds,
                             int64_t *lds_bytes_per_block);
 
+/* Launch-shape autotuner.  Times `segments` segments (rewl_run, or one
+ * rewl_run_persistent call if persistent != 0) for every walkers-per-block
+ * count in {1, 2, 4} and residency in {LDS, HBM} that the context can use,
+ * restoring the walk's state before each trial and at the end, so that the
+ * walk itself is unchanged; then applies the fastest shape.  entries[] (may
+ * be NULL) receives up to cap trials, *n_out (may be NULL) their number.
+ * Synchronises the stream; walkers must be initialised.  Needs host memory
+ * for one copy of the device buffers. */
+typedef struct {
+    int32_t walkers_per_block;
+    int32_t residency;         /* 1: configurations in LDS, 2: in HBM        */
+    int32_t persistent;        /* 1: timed with rewl_run_persistent          */
+    int32_t status;            /* REWL_OK, or why the shape was not usable   */
+    double ms_per_segment;     /* < 0 when not usable                        */
+} rewl_tune_entry;
+
+rewl_status rewl_autotune(rewl_ctx *ctx, int32_t segments, int32_t persistent, rewl_tune_entry *entries,
+                          int32_t cap, int32_t *n_out);
+
+/* 64-bit digest of everything that fixes the meaning of the context's
+ * buffers (mode, sizes, instance and lattice tables): equal digests mean
+ * interchangeable checkpoints and launch-shape choices. */
+rewl_status rewl_fingerprint(rewl_ctx *ctx, uint64_t *digest_out);
+
 /* Byte sizes of the REWL_NBUF device buffers the caller must provide. */
 rewl_status rewl_query_sizes(rewl_ctx *ctx, size_t *bytes_out /* [REWL_NBUF] */);
 

@@ -1116,4 +1116,151 @@ rewl_status rewl_load(rewl_ctx *ctx, const char *path)
     return REWL_OK;
 }
 
+
+rewl_status rewl_fingerprint(rewl_ctx *ctx, uint64_t *digest_out)
+{
+    if (!ctx || !digest_out) return fail(REWL_EINVAL, "null argument");
+    if (ctx->stage < 1) return fail(REWL_ESTATE, "call rewl_query_sizes first");
+    *digest_out = fingerprint(ctx);
+    return REWL_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- autotuner
+
+namespace {
+
+struct Snapshot {
+    std::vector<std::vector<unsigned char>> buf;
+    int64_t t = 0;
+};
+
+rewl_status take_snapshot(rewl_ctx *c, Snapshot &sn)
+{
+    rewl_status st = sync_check(c);
+    if (st) return st;
+    sn.buf.assign(REWL_NBUF, {});
+    for (int b = 0; b < REWL_NBUF; ++b) {
+        sn.buf[b].resize(c->sizes[b]);
+        if (c->sizes[b]) HIP_TRY(hipMemcpy(sn.buf[b].data(), c->buf[b], c->sizes[b], hipMemcpyDeviceToHost));
+    }
+    sn.t = c->t;
+    return REWL_OK;
+}
+
+rewl_status restore_snapshot(rewl_ctx *c, const Snapshot &sn)
+{
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int b = 0; b < REWL_NBUF; ++b)
+        if (c->sizes[b]) HIP_TRY(hipMemcpy(c->buf[b], sn.buf[b].data(), c->sizes[b], hipMemcpyHostToDevice));
+    c->t = sn.t;
+    return REWL_OK;
+}
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair()
+    {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+rewl_status rewl_autotune(rewl_ctx *ctx, int32_t segments, int32_t persistent, rewl_tune_entry *entries,
+                          int32_t cap, int32_t *n_out)
+{
+    if (!ctx) return fail(REWL_EINVAL, "null context");
+    if (ctx->stage < 3) return fail(REWL_ESTATE, "initialise walkers first");
+    if (segments < 1 || cap < 0) return fail(REWL_EINVAL, "need segments >= 1 and cap >= 0");
+    if (persistent && (ctx->mode == REWL_MODE_FP64_DET || ctx->fast_q <= 0))
+        return fail(REWL_EUNSUPPORTED, "the persistent kernel needs FP64 or FP32_DE mode on bcc lattices");
+    Snapshot sn;
+    rewl_status st = take_snapshot(ctx, sn);
+    if (st) return st;
+    const int32_t old_w = ctx->wpb_req, old_r = ctx->residency_req;
+    EventPair ev;
+    HIP_TRY(hipEventCreate(&ev.a));
+    HIP_TRY(hipEventCreate(&ev.b));
+    auto run = [&](int32_t n) -> rewl_status {
+        if (persistent) return rewl_run_persistent(ctx, n, 0, nullptr);
+        return rewl_run(ctx, n);
+    };
+    int32_t n = 0, best_w = 0, best_r = 0;
+    double best = -1.0;
+    const int wpbs[3] = {1, 2, 4};
+    for (int r = 1; r <= 2; ++r) {
+        for (int k = 0; k < 3; ++k) {
+            rewl_tune_entry e{};
+            e.walkers_per_block = wpbs[k];
+            e.residency = r;
+            e.persistent = persistent ? 1 : 0;
+            e.ms_per_segment = -1.0;
+            ctx->wpb_req = wpbs[k];
+            ctx->residency_req = r;
+            e.status = plan_launch(ctx);
+            if (e.status == REWL_OK) {
+                // one untimed segment (code and cache warm-up), then the trial
+                st = restore_snapshot(ctx, sn);
+                if (!st) st = run(1);
+                if (!st) st = restore_snapshot(ctx, sn);
+                if (!st) {
+                    if (hipEventRecord(ev.a, ctx->stream) != hipSuccess) st = REWL_EDEVICE;
+                }
+                if (!st) st = run(segments);
+                if (!st) {
+                    if (hipEventRecord(ev.b, ctx->stream) != hipSuccess || hipEventSynchronize(ev.b) != hipSuccess)
+                        st = REWL_EDEVICE;
+                }
+                if (!st) st = sync_check(ctx);
+                if (st == REWL_EUNSUPPORTED) {
+                    // the shape plans but cannot launch (no resident block)
+                    e.status = st;
+                    st = restore_snapshot(ctx, sn);
+                    if (st) return st;
+                    if (entries && n < cap) entries[n] = e;
+                    ++n;
+                    continue;
+                }
+                if (st) {
+                    // a failed trial leaves the walk restored and the old shape
+                    ctx->wpb_req = old_w;
+                    ctx->residency_req = old_r;
+                    plan_launch(ctx);
+                    rewl_status st2 = restore_snapshot(ctx, sn);
+                    return st2 ? st2 : st;
+                }
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
+                e.ms_per_segment = (double)ms / segments;
+                if (best < 0.0 || e.ms_per_segment < best) {
+                    best = e.ms_per_segment;
+                    best_w = wpbs[k];
+                    best_r = r;
+                }
+            }
+            if (entries && n < cap) entries[n] = e;
+            ++n;
+        }
+    }
+    st = restore_snapshot(ctx, sn);
+    if (st) return st;
+    if (best < 0.0) {
+        ctx->wpb_req = old_w;
+        ctx->residency_req = old_r;
+        plan_launch(ctx);
+        return fail(REWL_EUNSUPPORTED, "no launch shape is usable for this context");
+    }
+    ctx->wpb_req = best_w;
+    ctx->residency_req = best_r;
+    st = plan_launch(ctx);
+    if (st) return st;
+    if (n_out) *n_out = std::min(n, cap);
+    return REWL_OK;
+}
+
 }  // extern "C"

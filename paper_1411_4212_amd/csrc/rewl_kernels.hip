@@ -786,7 +786,10 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
     const double lnf = st.lnf;
     const bool frozen = st.done != 0;
     const bool discovering = (st.iter == 0) && !frozen;
+    // ln g and H of the current bin live in registers while the walker
+    // stays in it; LDS holds them again once it leaves and at the end
     double cur = uniform_d(Ld.lng[bin - ilo]);
+    uint32_t hcur = (uint32_t)__builtin_amdgcn_readfirstlane((int)Ld.H[bin - ilo]);
     const uint64_t n_begin = st.attempts;
     const uint64_t n_end = n_begin + (uint64_t)I.seg_len;
     uint64_t acc_count = 0, oow = 0;
@@ -941,15 +944,24 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
                 bool accept = false, outside = true;
                 int bb = 0;
                 double lnb = 0.0;
+                uint32_t hb = 0;
                 if (xb >= lo && xb < hi) {
                     bb = (int)floor(xb);
-                    lnb = uniform_d(Ld.lng[bb - ilo]);
+                    if (bb == bin) {
+                        lnb = cur;
+                        hb = hcur;
+                    } else {
+                        lnb = uniform_d(Ld.lng[bb - ilo]);
+                        hb = (uint32_t)__builtin_amdgcn_readfirstlane((int)Ld.H[bb - ilo]);
+                    }
                     outside = false;
                     if (__builtin_isnan(lnb)) {
                         if (discovering) {
                             lnb = cur;
                             Ld.lng[bb - ilo] = cur;
                             for (int j = lane; j < nb; j += kWave) Ld.H[j] = 0u;
+                            hb = 0u;
+                            hcur = 0u;
                         } else {
                             outside = true;
                         }
@@ -960,6 +972,12 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
                     }
                 }
                 oow += outside ? 1u : 0u;
+                if (accept && bb != bin) {
+                    // leave the current bin: its ln g and H back to LDS
+                    Ld.lng[bin - ilo] = cur;
+                    Ld.H[bin - ilo] = hcur;
+                    hcur = hb;
+                }
                 if (accept) {
                     if constexpr (LEARNED) {
                         if (lane == g) {
@@ -983,11 +1001,9 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
                     for (int q = 0; q < Q; ++q) hit |= (grp > g) && (nidx[q] == site);
                     stale = __builtin_amdgcn_ballot_w64(hit) != 0ull;
                 }
-                const int jb = bin - ilo;
                 if (!frozen) {
                     cur = cur + lnf;
-                    Ld.lng[jb] = cur;
-                    Ld.H[jb] = Ld.H[jb] + 1u;
+                    hcur = hcur + 1u;
                 }
                 if (trace && n < (uint64_t)a.trace_cap && lane == 0) {
                     rewl_trace_rec rec;
@@ -1003,6 +1019,9 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
         wave_sync();
     }
     const uint64_t n = n_end;
+    Ld.lng[bin - ilo] = cur;
+    Ld.H[bin - ilo] = hcur;
+    wave_sync();
 
     // resync when due (lane-parallel FP64 energy)
     LatCtx<MODE> c;

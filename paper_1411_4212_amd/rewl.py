@@ -39,6 +39,11 @@ class rewl_walker_state(C.Structure):
                 ("rejected_outside", C.c_uint64)]
 
 
+class rewl_tune_entry(C.Structure):
+    _fields_ = [("walkers_per_block", C.c_int32), ("residency", C.c_int32), ("persistent", C.c_int32),
+                ("status", C.c_int32), ("ms_per_segment", C.c_double)]
+
+
 class RewlError(RuntimeError):
     def __init__(self, fn, code, msg):
         super().__init__("%s failed (%d): %s" % (fn, code, msg))
@@ -75,6 +80,8 @@ _SIGS = {
     "rewl_write_lng": [_vp, _i32, _i32, _P(_dbl), _P(C.c_uint8), _i32],
     "rewl_save": [_vp, C.c_char_p],
     "rewl_run_persistent": [_vp, _i64, _i32, _P(_i32)],
+    "rewl_autotune": [_vp, _i32, _i32, _P(rewl_tune_entry), _i32, _P(_i32)],
+    "rewl_fingerprint": [_vp, _P(_u64)],
     "rewl_load": [_vp, C.c_char_p],
     "rewl_read_window": [_vp, _i32, _i32, _P(_i32), _P(_i32)],
     "rewl_read_exchange_stats": [_vp, _i32, _P(_u64), _P(_u64), _i32],
@@ -239,6 +246,19 @@ def rewl_run_persistent(ctx, max_rounds, max_blocks=0):
     g = _i32(0)
     _call("rewl_run_persistent", ctx, max_rounds, max_blocks, C.byref(g))
     return g.value
+
+
+def rewl_autotune(ctx, segments, persistent=False):
+    arr = (rewl_tune_entry * 6)()
+    n = _i32(0)
+    _call("rewl_autotune", ctx, segments, 1 if persistent else 0, arr, 6, C.byref(n))
+    return [{f: getattr(arr[k], f) for f, _ in rewl_tune_entry._fields_} for k in range(n.value)]
+
+
+def rewl_fingerprint(ctx):
+    d = _u64(0)
+    _call("rewl_fingerprint", ctx, C.byref(d))
+    return d.value
 
 
 def rewl_save(ctx, path):
@@ -450,6 +470,31 @@ class Run:
         """All instances advance up to max_rounds rounds in one launch;
         returns the grid size used."""
         return rewl_run_persistent(self.ctx, max_rounds, max_blocks)
+
+    def autotune(self, segments=2, persistent=False, cache=None):
+        """Choose walkers per block and residency by timing (the walk's state
+        is restored, so results do not change).  With `cache` (a JSON file
+        path) a shape chosen earlier for the same configuration digest is
+        applied without timing.  Returns the trials (empty when cached)."""
+        import json
+        key = "%016x/%s" % (rewl_fingerprint(self.ctx), "persistent" if persistent else "run")
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+            if key in table:
+                w, r = table[key]
+                rewl_set_launch(self.ctx, w, r)
+                return []
+        trials = rewl_autotune(self.ctx, segments, persistent)
+        if cache:
+            lc = rewl_get_launch(self.ctx)
+            table[key] = [lc["walkers_per_block"], 1 if lc["spins_in_lds"] else 2]
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(table, f, indent=1)
+            os.replace(tmp, cache)
+        return trials
 
     def save(self, path):
         rewl_save(self.ctx, path)

@@ -1,0 +1,68 @@
+"""Launch-shape autotuner (rewl_autotune): it times every usable walkers-
+per-block / residency shape, restores the walk's state around each trial,
+and applies the fastest; the walk that follows is bit-identical to one that
+never tuned (the shape does not change results).  A JSON cache keyed by the
+configuration digest reapplies the choice without timing."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from helpers import bits, gpu_from
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _cfgs():
+    mk = lambda L, J, win, seed=4: dict(lattice=("bcc", L, J), windows=win,
+                                       schedule=(4, 5, 1.0, 2.0 ** -10, 3000, 2 * L ** 3 * 100), seed=seed)
+    return [mk(4, [1.0, 0.5], (-600.0, -100.0, 60, 3, 0.75, 2)),
+            mk(6, [1.0, 0.6, -0.05, -0.1], (-1500.0, -300.0, 120, 4, 0.75, 3)),
+            mk(8, [1.0, 0.6, -0.05, -0.1], (-3500.0, -500.0, 200, 5, 0.75, 2))]
+
+
+def _state(g, cfgs):
+    out = []
+    for i, c in enumerate(cfgs):
+        for w in range(c["windows"][3] * c["windows"][5]):
+            out.append((bits(g.lng(i, w)).tolist(), g.hist(i, w).tolist(), sorted(g.walker(i, w).items())))
+    return out
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_autotune_restores_state_and_applies_fastest(persistent, tmp_path):
+    cfgs = _cfgs()
+    ref = gpu_from(cfgs, "fp32_de")
+    ref.run(2)
+    g = gpu_from(cfgs, "fp32_de")
+    g.run(2)
+    before = _state(g, cfgs)
+    cache = str(tmp_path / "tune.json")
+    trials = g.autotune(segments=2, persistent=persistent, cache=cache)
+    _say("trials", trials, "chosen", g.launch())
+    assert len(trials) == 6
+    ok = [t for t in trials if t["status"] == 0]
+    assert ok and all(t["ms_per_segment"] > 0 for t in ok)
+    best = min(ok, key=lambda t: t["ms_per_segment"])
+    lc = g.launch()
+    assert lc["walkers_per_block"] == best["walkers_per_block"]
+    assert lc["spins_in_lds"] == (best["residency"] == 1)
+    assert _state(g, cfgs) == before
+    assert g.step() == ref.step()
+    ref.run(3)
+    if persistent:
+        g.run_persistent(3)
+    else:
+        g.run(3)
+    assert _state(g, cfgs) == _state(ref, cfgs)
+    # a second context with the same configuration takes the cached shape
+    h = gpu_from(cfgs, "fp32_de")
+    assert h.autotune(segments=2, persistent=persistent, cache=cache) == []
+    assert h.launch() == lc
+    assert os.path.exists(cache)
