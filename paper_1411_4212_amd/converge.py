@@ -1,0 +1,114 @@
+"""Time to converged ln g with the uniform and with the learned proposal
+(the second half of the benchmark metric): wall-clock from the first sweep
+until every walker has finished its last ln f iteration, and the error of
+the joined ln g.  Library function plus a command line:
+
+    python -m paper_1411_4212_amd.converge --workload c4 --cap 600
+
+The learned run starts like the plain one; once every walker has reached
+ln f <= 2^-harvest_iter it records (x, S_i) of every k-th move for a few
+segments, trains the network on the device, switches to the learned
+proposal and continues to the end.  Its time includes harvest and training.
+Progress goes to stdout as one JSON line per chunk.
+"""
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+
+def _progress(r):
+    st = [r.walker(i, w) for i in range(len(r.inst)) for w in range(r.inst[i]["h"] * r.inst[i]["m"])]
+    lnf = np.array([s["lnf"] for s in st])
+    done = np.array([s["done"] for s in st])
+    att = sum(s["attempts"] for s in st)
+    acc = sum(s["accepts"] for s in st)
+    return dict(max_lnf=float(lnf.max()), min_iter=int(round(-math.log2(lnf.max()))),
+                done_frac=float(done.mean()), attempts=int(att), acceptance=acc / max(att, 1))
+
+
+def run(cfg, proposal="uniform", cap_s=600.0, rounds=64, harvest_iter=8, harvest_segments=4,
+        harvest_every=16, epochs=4, seed=None, tag=""):
+    import torch
+    from . import analysis, learned, workloads
+    from .rewl import Run
+    r = Run([dict(lattice=cfg["lattice"], windows=cfg["windows"], schedule=cfg["schedule"])], mode="fp32_de")
+    r.init(cfg["seed"] if seed is None else seed, workloads.init_spins(cfg))
+    dev = torch.device("cuda", 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    phase = "plain"
+    info = {}
+    done = False
+    while True:
+        r.run_persistent(rounds)
+        done = bool(r.poll())
+        p = _progress(r)
+        el = time.perf_counter() - t0
+        print(json.dumps(dict(tag=tag, proposal=proposal, phase=phase, seconds=round(el, 2), **p)), flush=True)
+        if done or el > cap_s:
+            break
+        if proposal == "learned" and phase == "plain" and p["max_lnf"] <= 2.0 ** -harvest_iter:
+            th = time.perf_counter()
+            seg = cfg["schedule"][4]
+            cap = harvest_segments * seg // harvest_every + 1
+            r.set_harvest(cap, harvest_every)
+            r.run(harvest_segments)
+            recs = r.harvested()
+            from .rewl import rewl_set_harvest
+            rewl_set_harvest(r.ctx, None, 0, 1)
+            params = learned.init_params(1, dev)
+            losses = learned.train(recs, params, epochs=epochs, batch=4096, lr=2e-3, seed=3)
+            r.set_proposal(params)
+            torch.cuda.synchronize()
+            info = dict(records=int(recs.shape[0]), loss=[round(float(x), 4) for x in losses],
+                        harvest_train_s=round(time.perf_counter() - th, 2))
+            print(json.dumps(dict(tag=tag, event="switched to learned proposal", **info)), flush=True)
+            del recs
+            phase = "learned"
+    seconds = time.perf_counter() - t0
+    bins, lng = analysis.run_lng(r, 0)
+    res = dict(tag=tag, proposal=proposal, seconds=seconds, done=done, **_progress(r), **info)
+    r.close()
+    return res, bins, lng
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="c4")
+    ap.add_argument("--cap", type=float, default=600.0, help="seconds per run")
+    ap.add_argument("--lnf-final-exp", type=int, default=20, help="run to ln f = 2^-this")
+    ap.add_argument("--proposals", default="uniform,learned")
+    ap.add_argument("--seeds", default="0")
+    ap.add_argument("--out", default=None, help="write the joined ln g of every run (npz)")
+    args = ap.parse_args()
+    from . import workloads
+    cfg = getattr(workloads, args.workload)()
+    s = list(cfg["schedule"])
+    s[3] = 2.0 ** -args.lnf_final_exp
+    cfg["schedule"] = tuple(s)
+    results, curves = [], {}
+    for seed in [int(x) for x in args.seeds.split(",")]:
+        for prop in args.proposals.split(","):
+            tag = "%s/seed%d" % (prop, seed)
+            res, bins, lng = run(cfg, prop, args.cap, seed=seed, tag=tag)
+            results.append(res)
+            curves[tag] = lng
+            print(json.dumps(dict(result=res)), flush=True)
+    keys = list(curves)
+    for i in range(len(keys)):
+        for j in range(i + 1, len(keys)):
+            a, b = curves[keys[i]], curves[keys[j]]
+            ok = np.isfinite(a) & np.isfinite(b)
+            d = (a - a[ok].mean()) - (b - b[ok].mean())
+            print(json.dumps(dict(compare=[keys[i], keys[j]], max_abs_dlng=float(np.abs(d[ok]).max()),
+                                  rms_dlng=float(np.sqrt(np.mean(d[ok] ** 2))), bins=int(ok.sum()))), flush=True)
+    if args.out:
+        np.savez(args.out, **{k.replace("/", "_"): v for k, v in curves.items()})
+
+
+if __name__ == "__main__":
+    sys.exit(main())
