@@ -360,6 +360,15 @@ rewl_status rewl_read_harvest_counts(rewl_ctx *ctx, int64_t *counts, int32_t cap
 rewl_status rewl_save(rewl_ctx *ctx, const char *path);
 rewl_status rewl_load(rewl_ctx *ctx, const char *path);
 
+/* Replica diffusion (the paper's Fig. 1, Sec. results): for each of the
+ * instance's configurations (index = the `config` field of the walker
+ * states), the number of half round trips between the lowest and the
+ * highest window, counted at exchange steps (a configuration held by a
+ * walker of an extreme window whose last extreme visited was the other
+ * one).  half_trips: host, min(cap, walkers of the instance) entries.
+ * Synchronises the stream. */
+rewl_status rewl_read_round_trips(rewl_ctx *ctx, int32_t inst, uint32_t *half_trips, int32_t cap);
+
 /* Totals over all walkers of the context (synchronising). */
 rewl_status rewl_total_attempts(rewl_ctx *ctx, uint64_t *attempts, uint64_t *accepts);
 

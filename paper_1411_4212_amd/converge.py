@@ -26,11 +26,14 @@ def _progress(r):
     done = np.array([s["done"] for s in st])
     att = sum(s["attempts"] for s in st)
     acc = sum(s["accepts"] for s in st)
+    it = np.array([s["iteration"] for s in st])
+    hist = np.bincount(it, minlength=int(it.max()) + 1)
     return dict(max_lnf=float(lnf.max()), min_iter=int(round(-math.log2(lnf.max()))),
-                done_frac=float(done.mean()), attempts=int(att), acceptance=acc / max(att, 1))
+                done_frac=float(done.mean()), attempts=int(att), acceptance=acc / max(att, 1),
+                iter_hist=hist.tolist())
 
 
-def run(cfg, proposal="uniform", cap_s=600.0, rounds=64, harvest_iter=8, harvest_segments=4,
+def run(cfg, proposal="uniform", cap_s=600.0, rounds=256, harvest_iter=8, harvest_segments=4,
         harvest_every=16, epochs=4, seed=None, tag=""):
     import torch
     from . import analysis, learned, workloads
@@ -70,6 +73,18 @@ def run(cfg, proposal="uniform", cap_s=600.0, rounds=64, harvest_iter=8, harvest
             del recs
             phase = "learned"
     seconds = time.perf_counter() - t0
+    slow = []
+    for w in range(r.n_walkers):
+        s_ = r.walker(0, w)
+        if s_["iteration"] == min(x["iteration"] for x in [s_]) and s_["iteration"] <= _progress(r)["min_iter"]:
+            h_ = r.hist(0, w)
+            v_ = r.visited(0, w).astype(bool)
+            slow.append(dict(walker=w, window=s_["window"], iteration=s_["iteration"], n_visited=s_["n_visited"],
+                             bins=int(v_.size), bin=s_["bin"], H_min=int(h_[v_].min()) if v_.any() else 0,
+                             H_mean=float(h_[v_].mean()) if v_.any() else 0.0))
+        if len(slow) >= 12:
+            break
+    print(json.dumps(dict(tag=tag, slowest_walkers=slow)), flush=True)
     bins, lng = analysis.run_lng(r, 0)
     res = dict(tag=tag, proposal=proposal, seconds=seconds, done=done, **_progress(r), **info)
     r.close()

@@ -103,7 +103,7 @@ struct rewl_ctx {
     size_t off_inst = 0, off_wdesc = 0, off_slots = 0, off_tdeg = 0, off_tnbr = 0, off_tJ = 0,
            off_init = 0;
     // CONTROL layout
-    size_t off_ictl = 0, off_xatt = 0, off_xacc = 0;
+    size_t off_ictl = 0, off_xatt = 0, off_xacc = 0, off_rtrip = 0;
     size_t off_pctl = 0, off_parr = 0, off_prnd = 0, off_pslots = 0;
     uint32_t p_cap = 0;
     int32_t last_grid = 0;
@@ -162,6 +162,7 @@ KArgs make_args(rewl_ctx *c)
     a.ictl = (InstControl *)(Cb + c->off_ictl);
     a.xatt = (unsigned long long *)(Cb + c->off_xatt);
     a.xacc = (unsigned long long *)(Cb + c->off_xacc);
+    a.rtrip = (uint32_t *)(Cb + c->off_rtrip);
     a.pctl = (PersistCtl *)(Cb + c->off_pctl);
     a.p_arrive = (uint32_t *)(Cb + c->off_parr);
     a.p_rounds = (uint32_t *)(Cb + c->off_prnd);
@@ -426,6 +427,8 @@ rewl_status finalize(rewl_ctx *c)
     oc = align256(oc + sizeof(unsigned long long) * (size_t)c->n_xstat);
     c->off_xacc = oc;
     oc = align256(oc + sizeof(unsigned long long) * (size_t)c->n_xstat);
+    c->off_rtrip = oc;
+    oc = align256(oc + sizeof(uint32_t) * (size_t)c->n_walkers);
     // persistent-kernel queue: capacity a power of two above every walker
     // plus every wavefront that may hold a ticket
     c->p_cap = 256;
@@ -968,6 +971,22 @@ rewl_status rewl_read_step(rewl_ctx *ctx, int64_t *step_out)
 {
     if (!ctx || !step_out) return fail(REWL_EINVAL, "null argument");
     *step_out = ctx->t;
+    return REWL_OK;
+}
+
+rewl_status rewl_read_round_trips(rewl_ctx *ctx, int32_t inst, uint32_t *half_trips, int32_t cap)
+{
+    if (!ctx || !half_trips || cap < 0) return fail(REWL_EINVAL, "bad argument");
+    if (ctx->stage < 3) return fail(REWL_ESTATE, "walkers not initialised");
+    if (inst < 0 || inst >= (int32_t)ctx->inst.size()) return fail(REWL_EINVAL, "bad instance index");
+    rewl_status st = sync_check(ctx);
+    if (st) return st;
+    const InstDesc &d = ctx->idesc[inst];
+    const int32_t n = std::min(d.n_walkers, cap);
+    std::vector<uint32_t> v(n);
+    HIP_TRY(hipMemcpy(v.data(), (unsigned char *)ctx->buf[REWL_BUF_CONTROL] + ctx->off_rtrip + 4 * (size_t)d.walker_base,
+                      4 * (size_t)n, hipMemcpyDeviceToHost));
+    for (int32_t k = 0; k < n; ++k) half_trips[k] = v[k] >> 2;
     return REWL_OK;
 }
 

@@ -98,6 +98,7 @@ struct KArgs {
     InstControl *ictl;
     unsigned long long *xatt;
     unsigned long long *xacc;
+    uint32_t *rtrip;           // per configuration: (half trips << 2) | last extreme window (1 low, 2 high)
     rewl_trace_rec *trace;
     int64_t trace_cap;
     int64_t t;                 // exchange step counter

@@ -615,6 +615,23 @@ __device__ void exchange_instance(const KArgs &a, int ii, uint64_t t)
             __hip_atomic_fetch_add(a.xacc + I.xstat_off + k, nacc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
+    // round trips of configurations between the lowest and the highest
+    // window (the replica diffusion the paper follows in its Fig. 1): a
+    // half trip is counted when a configuration held in an extreme window
+    // last visited the other extreme
+    if (I.h >= 2) {
+        // the swaps above were stored by other lanes of this wavefront
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        for (int j = lane; j < 2 * m; j += kWave) {
+            const int win = j < m ? 0 : I.h - 1;
+            const int w = I.walker_base + win * m + (j < m ? j : j - m);
+            const int c = a.state[w].cfg;
+            uint32_t *e = a.rtrip + I.walker_base + c;
+            const uint32_t ext = j < m ? 1u : 2u;
+            const uint32_t v = *e;
+            if ((v & 3u) != ext) *e = ((v & ~3u) + ((v & 3u) ? 4u : 0u)) | ext;
+        }
+    }
     bool running = false;
     for (int w = lane; w < I.n_walkers; w += kWave) running |= (a.state[I.walker_base + w].done == 0);
     const bool all_done = __builtin_amdgcn_ballot_w64(running) == 0ull;

@@ -79,6 +79,7 @@ _SIGS = {
     "rewl_read_config": [_vp, _i32, _i32, _P(_dbl), _i64],
     "rewl_write_lng": [_vp, _i32, _i32, _P(_dbl), _P(C.c_uint8), _i32],
     "rewl_save": [_vp, C.c_char_p],
+    "rewl_read_round_trips": [_vp, _i32, _P(C.c_uint32), _i32],
     "rewl_run_persistent": [_vp, _i64, _i32, _P(_i32)],
     "rewl_autotune": [_vp, _i32, _i32, _P(rewl_tune_entry), _i32, _P(_i32)],
     "rewl_fingerprint": [_vp, _P(_u64)],
@@ -259,6 +260,12 @@ def rewl_fingerprint(ctx):
     d = _u64(0)
     _call("rewl_fingerprint", ctx, C.byref(d))
     return d.value
+
+
+def rewl_read_round_trips(ctx, inst, n):
+    out = np.zeros(n, dtype=np.uint32)
+    _call("rewl_read_round_trips", ctx, inst, out.ctypes.data_as(_P(C.c_uint32)), n)
+    return out
 
 
 def rewl_save(ctx, path):
@@ -495,6 +502,10 @@ class Run:
                 json.dump(table, f, indent=1)
             os.replace(tmp, cache)
         return trials
+
+    def round_trips(self, inst):
+        """Half round trips (lowest <-> highest window) per configuration."""
+        return rewl_read_round_trips(self.ctx, inst, self.inst[inst]["h"] * self.inst[inst]["m"])
 
     def save(self, path):
         rewl_save(self.ctx, path)

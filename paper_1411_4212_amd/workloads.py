@@ -143,27 +143,43 @@ def _bins_for(h, per_window=100, overlap=0.75):
     return int(round(per_window * (1 + (h - 1) * (1 - overlap))))
 
 
+def _bins_for_width(E_range, h, dE, overlap=0.75, cap=4096):
+    """Global bin count giving bins of about dE J, with at most `cap` bins
+    per window."""
+    Emin, Emax = E_range
+    B = int(round((Emax - Emin) / dE))
+    per = B / (1 + (h - 1) * (1 - overlap))
+    if per > cap:
+        B = int(math.floor(cap * (1 + (h - 1) * (1 - overlap))))
+    return B
+
+
 def c4():
     """bcc L=16 (8192 spins), eight shells J_n = exp(-0.6 (n-1)) (-1)^[n>5];
-    64 windows x 16 walkers, 100 bins per window, o = 0.75; ln f to 2^-20;
-    exchange every 1e4 moves; start from the ferromagnet."""
+    64 windows x 16 walkers, o = 0.75, bins of about 3 J (about 1250 per
+    window); ln f to 2^-20; exchange every 1e4 moves; start from the
+    ferromagnet.  The bin width is fixed in energy, not in bins per window:
+    ln g must change little across a bin at the lowest temperatures the
+    range reaches, else a walker is trapped at a window edge by the entropy
+    gradient inside one bin (the paper leaves the bin width open)."""
     L, h, m = 16, 64, 16
     N = 2 * L ** 3
     Emin, Emax = paper_cut(L, J8)
     return dict(name="bcc_L16_J8_64x16", lattice=("bcc", L, list(J8)),
-                windows=(Emin, Emax, _bins_for(h), h, 0.75, m),
+                windows=(Emin, Emax, _bins_for_width((Emin, Emax), h, 3.0), h, 0.75, m),
                 schedule=(4, 5, 1.0, 2.0 ** -20, 10000, 100 * N), seed=0, init="ferro")
 
 
 def c5():
     """bcc L=32 (65536 spins, configurations in HBM), the eight shells of
-    c4; 128 windows x 8 walkers, 100 bins per window; ln f to 2^-20;
-    exchange every 1e4 moves; start from the ferromagnet."""
+    c4; 128 windows x 8 walkers, bins of about 4 J (3840 per window, close
+    to the 4096 limit); ln f to 2^-20; exchange every 1e4 moves; start from
+    the ferromagnet."""
     L, h, m = 32, 128, 8
     N = 2 * L ** 3
     Emin, Emax = paper_cut(L, J8)
     return dict(name="bcc_L32_J8_128x8", lattice=("bcc", L, list(J8)),
-                windows=(Emin, Emax, _bins_for(h), h, 0.75, m),
+                windows=(Emin, Emax, _bins_for_width((Emin, Emax), h, 4.0), h, 0.75, m),
                 schedule=(4, 5, 1.0, 2.0 ** -20, 10000, 100 * N), seed=0, init="ferro")
 
 
