@@ -46,15 +46,19 @@ def run(cfg, proposal="uniform", cap_s=600.0, rounds=256, harvest_iter=8, harves
     phase = "plain"
     info = {}
     done = False
+    done_at = np.full(r.n_walkers, np.nan)
     while True:
         r.run_persistent(rounds)
         done = bool(r.poll())
         p = _progress(r)
         el = time.perf_counter() - t0
+        dn = np.array([r.walker(0, w)["done"] for w in range(r.n_walkers)], dtype=bool)
+        done_at[dn & np.isnan(done_at)] = el
         print(json.dumps(dict(tag=tag, proposal=proposal, phase=phase, seconds=round(el, 2), **p)), flush=True)
         if done or el > cap_s:
             break
-        if proposal == "learned" and phase == "plain" and p["max_lnf"] <= 2.0 ** -harvest_iter:
+        its = np.repeat(np.arange(len(p["iter_hist"])), p["iter_hist"])
+        if proposal == "learned" and phase == "plain" and np.median(its) >= harvest_iter:
             th = time.perf_counter()
             seg = cfg["schedule"][4]
             cap = harvest_segments * seg // harvest_every + 1
@@ -86,7 +90,12 @@ def run(cfg, proposal="uniform", cap_s=600.0, rounds=256, harvest_iter=8, harves
             break
     print(json.dumps(dict(tag=tag, slowest_walkers=slow)), flush=True)
     bins, lng = analysis.run_lng(r, 0)
-    res = dict(tag=tag, proposal=proposal, seconds=seconds, done=done, **_progress(r), **info)
+    fr = {}
+    for q in (50, 75, 90, 100):
+        k = int(math.ceil(q / 100.0 * r.n_walkers))
+        srt = np.sort(done_at)
+        fr["t_done_%d%%" % q] = None if np.isnan(srt[k - 1]) else round(float(srt[k - 1]), 1)
+    res = dict(tag=tag, proposal=proposal, seconds=seconds, done=done, **fr, **_progress(r), **info)
     r.close()
     return res, bins, lng
 
@@ -112,8 +121,10 @@ def main():
             res, bins, lng = run(cfg, prop, args.cap, seed=seed, tag=tag)
             results.append(res)
             curves[tag] = lng
+            for k, v in run.last_fragments.items():
+                curves[tag + "/" + k] = v
             print(json.dumps(dict(result=res)), flush=True)
-    keys = list(curves)
+    keys = [k for k in curves if k.count("/") == 1]
     for i in range(len(keys)):
         for j in range(i + 1, len(keys)):
             a, b = curves[keys[i]], curves[keys[j]]

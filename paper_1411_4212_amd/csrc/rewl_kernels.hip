@@ -814,6 +814,11 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
     const uint32_t wrapC = 0x00808080u - 0x00010101u * (uint32_t)fl.L;   // 128 - L per 8-bit field
 
     int nidx[Q];
+    // the site and proposal of this lane's group move, kept in registers so
+    // that an accepted move needs no LDS round trip to write its spin or to
+    // find the later moves it invalidates
+    int mv_site = 0;
+    V mv_prop{};
     T dEv = 0;
     T hx_k = 0, hy_k = 0, hz_k = 0;          // this lane's group field (harvest)
     V si_k{};
@@ -832,6 +837,8 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
         // the site's own spin and the proposal are read with the gather
         const V si = S[site];
         const V pr = b_prop[e];
+        mv_site = site;
+        mv_prop = pr;
         T px = 0, py = 0, pz = 0;
         const int sb = (POW2 || fl.pow2) ? (code >> (3 * fl.k)) : (code >> 24);
 #pragma unroll
@@ -929,6 +936,7 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
         }
         wave_sync();
         const int nvalid = (int)((n_end - n0) < 64 ? (n_end - n0) : 64);
+        const bool trace_b = trace != nullptr && n0 < (uint64_t)a.trace_cap;
         for (int p = 0; p < nvalid; p += 4) {
             fields(p);
             bool stale = false;
@@ -963,7 +971,7 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
                 double lnb = 0.0;
                 uint32_t hb = 0;
                 if (xb >= lo && xb < hi) {
-                    bb = (int)floor(xb);
+                    bb = (int)xb;   // xb >= lo >= 0: truncation is the floor
                     if (bb == bin) {
                         lnb = cur;
                         hb = hcur;
@@ -1006,14 +1014,14 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
                             S[site] = v;
                         }
                     } else {
-                        if (lane == 16 * g) S[site] = b_prop[p + g];
+                        if (lane == 16 * g) S[site] = mv_prop;
                     }
                     E = Eb;
                     bin = bb;
                     cur = lnb;
                     ++acc_count;
                     // later moves of this pass whose neighbourhood or site changed
-                    bool hit = (grp > g) && (b_site[p + grp] == site);
+                    bool hit = (grp > g) && (mv_site == site);
 #pragma unroll
                     for (int q = 0; q < Q; ++q) hit |= (grp > g) && (nidx[q] == site);
                     stale = __builtin_amdgcn_ballot_w64(hit) != 0ull;
@@ -1022,7 +1030,7 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
                     cur = cur + lnf;
                     hcur = hcur + 1u;
                 }
-                if (trace && n < (uint64_t)a.trace_cap && lane == 0) {
+                if (trace_b && n < (uint64_t)a.trace_cap && lane == 0) {
                     rewl_trace_rec rec;
                     rec.site = (uint32_t)site;
                     rec.flags = (accept ? 1u : 0u) | (outside ? 2u : 0u);
