@@ -77,19 +77,31 @@ def run(cfg, proposal="uniform", cap_s=600.0, rounds=256, harvest_iter=8, harves
             del recs
             phase = "learned"
     seconds = time.perf_counter() - t0
+    states = [r.walker(0, w) for w in range(r.n_walkers)]
+    order = sorted(range(r.n_walkers), key=lambda w: states[w]["iteration"])[:12]
     slow = []
-    for w in range(r.n_walkers):
-        s_ = r.walker(0, w)
-        if s_["iteration"] == min(x["iteration"] for x in [s_]) and s_["iteration"] <= _progress(r)["min_iter"]:
-            h_ = r.hist(0, w)
-            v_ = r.visited(0, w).astype(bool)
-            slow.append(dict(walker=w, window=s_["window"], iteration=s_["iteration"], n_visited=s_["n_visited"],
-                             bins=int(v_.size), bin=s_["bin"], H_min=int(h_[v_].min()) if v_.any() else 0,
-                             H_mean=float(h_[v_].mean()) if v_.any() else 0.0))
-        if len(slow) >= 12:
-            break
+    for w in order:
+        h_ = r.hist(0, w)
+        v_ = r.visited(0, w).astype(bool)
+        slow.append(dict(walker=w, window=states[w]["window"], iteration=states[w]["iteration"],
+                         n_visited=states[w]["n_visited"], bins=int(v_.size), bin=states[w]["bin"],
+                         H_min=int(h_[v_].min()) if v_.any() else 0,
+                         H_mean=float(h_[v_].mean()) if v_.any() else 0.0))
     print(json.dumps(dict(tag=tag, slowest_walkers=slow)), flush=True)
-    bins, lng = analysis.run_lng(r, 0)
+    try:
+        bins, lng = analysis.run_lng(r, 0)
+    except ValueError as e:          # windows not yet joinable
+        print(json.dumps(dict(tag=tag, join_failed=str(e))), flush=True)
+        bins = np.arange(cfg["windows"][2])
+        lng = np.full(cfg["windows"][2], np.nan)
+    # per-window combined ln g of the windows whose walkers are all done
+    inst = r.inst[0]
+    frags = {}
+    for k in range(inst["h"]):
+        ws = range(k * inst["m"], (k + 1) * inst["m"])
+        if all(r.walker(0, w)["done"] for w in ws):
+            lg_k, vis_k = analysis.combine_walkers([r.lng(0, w) for w in ws], [r.visited(0, w) for w in ws])
+            frags["win%03d" % k] = np.where(vis_k, lg_k, np.nan)
     fr = {}
     for q in (50, 75, 90, 100):
         k = int(math.ceil(q / 100.0 * r.n_walkers))
@@ -97,7 +109,7 @@ def run(cfg, proposal="uniform", cap_s=600.0, rounds=256, harvest_iter=8, harves
         fr["t_done_%d%%" % q] = None if np.isnan(srt[k - 1]) else round(float(srt[k - 1]), 1)
     res = dict(tag=tag, proposal=proposal, seconds=seconds, done=done, **fr, **_progress(r), **info)
     r.close()
-    return res, bins, lng
+    return res, bins, lng, frags
 
 
 def main():
@@ -118,10 +130,10 @@ def main():
     for seed in [int(x) for x in args.seeds.split(",")]:
         for prop in args.proposals.split(","):
             tag = "%s/seed%d" % (prop, seed)
-            res, bins, lng = run(cfg, prop, args.cap, seed=seed, tag=tag)
+            res, bins, lng, frags = run(cfg, prop, args.cap, seed=seed, tag=tag)
             results.append(res)
             curves[tag] = lng
-            for k, v in run.last_fragments.items():
+            for k, v in frags.items():
                 curves[tag + "/" + k] = v
             print(json.dumps(dict(result=res)), flush=True)
     keys = [k for k in curves if k.count("/") == 1]
@@ -133,7 +145,7 @@ def main():
             print(json.dumps(dict(compare=[keys[i], keys[j]], max_abs_dlng=float(np.abs(d[ok]).max()),
                                   rms_dlng=float(np.sqrt(np.mean(d[ok] ** 2))), bins=int(ok.sum()))), flush=True)
     if args.out:
-        np.savez(args.out, **{k.replace("/", "_"): v for k, v in curves.items()})
+        np.savez(args.out, **{k.replace("/", "__"): v for k, v in curves.items()})
 
 
 if __name__ == "__main__":
