@@ -966,36 +966,30 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
                 const double lnu = readlane_d(my_lnu, p + g);
                 const double Eb = E + dE;
                 const double xb = __builtin_fma(Eb, inv, -emin_inv);
-                bool accept = false, outside = true;
-                int bb = 0;
-                double lnb = 0.0;
-                uint32_t hb = 0;
-                if (xb >= lo && xb < hi) {
-                    bb = (int)xb;   // xb >= lo >= 0: truncation is the floor
-                    if (bb == bin) {
+                // ln g and H of the proposed bin, read without a branch: a
+                // proposal outside the window reads the current bin instead
+                const bool inwin = (xb >= lo) && (xb < hi);
+                const int bb = (int)(inwin ? xb : (double)bin);   // xb >= lo >= 0: truncation is the floor
+                const double lnb_m = Ld.lng[bb - ilo];
+                const uint32_t hb_m = Ld.H[bb - ilo];
+                const bool same = bb == bin;
+                double lnb = same ? cur : lnb_m;
+                uint32_t hb = same ? hcur : hb_m;
+                bool outside = !inwin;
+                if (inwin && __builtin_isnan(lnb)) {
+                    // a bin not visited yet
+                    if (discovering) {
                         lnb = cur;
-                        hb = hcur;
+                        Ld.lng[bb - ilo] = cur;
+                        for (int j = lane; j < nb; j += kWave) Ld.H[j] = 0u;
+                        hb = 0u;
+                        hcur = 0u;
                     } else {
-                        lnb = uniform_d(Ld.lng[bb - ilo]);
-                        hb = (uint32_t)__builtin_amdgcn_readfirstlane((int)Ld.H[bb - ilo]);
-                    }
-                    outside = false;
-                    if (__builtin_isnan(lnb)) {
-                        if (discovering) {
-                            lnb = cur;
-                            Ld.lng[bb - ilo] = cur;
-                            for (int j = lane; j < nb; j += kWave) Ld.H[j] = 0u;
-                            hb = 0u;
-                            hcur = 0u;
-                        } else {
-                            outside = true;
-                        }
-                    }
-                    if (!outside) {
-                        const double lr = (cur - lnb) + lnqr;
-                        accept = (lr >= 0.0) || (lnu < lr);
+                        outside = true;
                     }
                 }
+                const double lr = (cur - lnb) + lnqr;
+                const bool accept = !outside && ((lr >= 0.0) || (lnu < lr));
                 oow += outside ? 1u : 0u;
                 if (accept && bb != bin) {
                     // leave the current bin: its ln g and H back to LDS
