@@ -988,8 +988,10 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
                         outside = true;
                     }
                 }
-                const double lr = (cur - lnb) + lnqr;
-                const bool accept = !outside && ((lr >= 0.0) || (lnu < lr));
+                // ln u < 0 always, so ln u < lr also covers lr >= 0; the q-ratio
+                // term only exists with the learned proposal
+                const double lr = LEARNED ? (cur - lnb) + lnqr : (cur - lnb);
+                const bool accept = !outside && (lnu < lr);
                 oow += outside ? 1u : 0u;
                 if (accept && bb != bin) {
                     // leave the current bin: its ln g and H back to LDS
