@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0
 # were taken on (a changed kernel reports null until measured again).
 MEASURED_TRAFFIC = {
     # profiles/sweep_fast_c2_fp32_counters.md: FETCH 1361.0 KiB x 2.00 + WRITE 2754.5 KiB x 1.00
-    ("0f3d8ad28057a0d0", "fp32_de"): 5608000,
+    ("0f3d8ad28057a0d0", "fp32_de", "lds"): 5608000,
 }
 KERNEL_SOURCES = ["rewl_kernels.hip", "rewl_device.h", "rewl_internal.h", "rewl_mlp_device.h"]
 
@@ -51,6 +51,14 @@ def bytes_per_attempt(z, mode):
     the ln g + H update of the current bin (read + write)."""
     s = 12 if mode == "fp32_de" else 24
     return z * s + s + 8 + (8 + 4) * 2
+
+
+def hbm_bytes_per_attempt(z, mode):
+    """Algorithmic HBM bytes of one trial move when the configurations stay in
+    HBM: the z neighbour spins and the site's own spin (3 components each);
+    ln g and H stay in LDS for the segment."""
+    s = 12 if mode == "fp32_de" else 24
+    return (z + 1) * s
 
 
 def cpu_baseline(cfg, seconds):
@@ -93,9 +101,10 @@ def _timed(r, fn, torch):
 
 def extra_measurements(torch, workloads, Run):
     """The same kernels on workloads that fill the chip (reported beside the
-    headline figure): the 64 uneven instances in the persistent kernel with
-    an autotuned launch shape, and the L=16 eight-shell workload (1024
-    walkers) with the uniform and with the learned proposal."""
+    headline figure), each with an autotuned launch shape: the 64 uneven
+    instances in the persistent kernel, the L=16 eight-shell workload (1024
+    walkers) with the uniform and with the learned proposal, and the L=32
+    workload (1024 walkers, 65,536 spins each)."""
     import numpy as np
     out = {}
     cfgs = workloads.batched(64)
@@ -113,19 +122,26 @@ def extra_measurements(torch, workloads, Run):
                                     (round(t["ms_per_segment"], 3) if t["status"] == 0 else None) for t in trials}}
     r.close()
     log("bench: batched %.3e attempts/s" % rate)
-    c4 = workloads.c4()
     from paper_1411_4212_amd import learned
-    for kind in ("uniform", "learned"):
-        r = Run([dict(lattice=c4["lattice"], windows=c4["windows"], schedule=c4["schedule"])], mode="fp32_de")
-        r.init(c4["seed"], workloads.init_spins(c4))
-        if kind == "learned":
-            r.set_proposal(learned.init_params(1, torch.device("cuda", 0)))
-        r.run(1)
-        rate, dt = _timed(r, lambda: r.run(2), torch)
-        out["L16_8shell_%s" % kind] = {"walkers": r.n_walkers, "attempts_per_s": rate, "seconds": dt,
-                                       "segments": 2, "proposal": kind}
-        r.close()
-        log("bench: L16 %s %.3e attempts/s" % (kind, rate))
+    for name, wl, kinds in (("L16_8shell", workloads.c4(), ("uniform", "learned")),
+                            ("L32_8shell", workloads.c5(), ("uniform",))):
+        for kind in kinds:
+            r = Run([dict(lattice=wl["lattice"], windows=wl["windows"], schedule=wl["schedule"])], mode="fp32_de")
+            r.init(wl["seed"], workloads.init_spins(wl))
+            if kind == "learned":
+                r.set_proposal(learned.init_params(1, torch.device("cuda", 0)))
+            r.autotune(segments=1)
+            lc = r.launch()
+            rate, dt = _timed(r, lambda: r.run(2), torch)
+            z = 112
+            out["%s_%s" % (name, kind)] = {
+                "walkers": r.n_walkers, "attempts_per_s": rate, "seconds": dt, "segments": 2, "proposal": kind,
+                "walkers_per_block": lc["walkers_per_block"], "spins_in_lds": lc["spins_in_lds"],
+                # algorithmic gather bytes per attempt (z neighbour spins + own spin, 16 B each)
+                # when the configurations are read from HBM
+                "gather_GBs_if_hbm": None if lc["spins_in_lds"] else rate * (z + 1) * 16 / 1e9}
+            r.close()
+            log("bench: %s %s %.3e attempts/s (%s)" % (name, kind, rate, "LDS" if lc["spins_in_lds"] else "HBM"))
     return out
 
 
@@ -137,6 +153,8 @@ def main():
     ap.add_argument("--mode", default="fp32_de", choices=["fp32_de", "fp64", "fp64_det"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shape instead of the autotuner's choice")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the chip-filling workloads reported under 'extra'")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -160,9 +178,15 @@ def main():
     log("bench: building run", cfg["name"], args.mode)
     r = Run([dict(lattice=lat, windows=cfg["windows"], schedule=cfg["schedule"])], mode=args.mode)
     r.init(cfg["seed"])
+    if not args.no_autotune:
+        # launch shape by the project's autotuner (the walk is restored after
+        # every trial, so the timed steps start from the initialised state)
+        r.autotune(segments=2)
+    lc = r.launch()
+    in_lds = bool(lc["spins_in_lds"])
     W = r.n_walkers
     seg = cfg["schedule"][4]
-    log("bench: warmup", args.warmup)
+    log("bench: warmup", args.warmup, "launch", lc)
     for _ in range(args.warmup):
         r.sweep()
         r.exchange()
@@ -186,7 +210,11 @@ def main():
     wall = t1 - t0
     sweep_ms = [s.elapsed_time(e) for s, e in evs]
     avg_sweep_s = sum(sweep_ms) / len(sweep_ms) / 1e3
-    per_launch_bytes = bytes_per_attempt(zsum, args.mode) * W * seg
+    if in_lds:
+        bpa, bound, peak = bytes_per_attempt(zsum, args.mode), "lds", LDS_PEAK_GBS
+    else:
+        bpa, bound, peak = hbm_bytes_per_attempt(zsum, args.mode), "hbm", HBM_PEAK_GBS
+    per_launch_bytes = bpa * W * seg
     achieved = per_launch_bytes / avg_sweep_s / 1e9
     log("bench: %.3e attempts/s, sweep %.3f ms avg" % (attempts / wall, avg_sweep_s * 1e3))
     if args.calibrate_copy:
@@ -197,7 +225,7 @@ def main():
         torch.cuda.synchronize()
         log("bench: copy calibration done (3 x 256 MiB)")
     digest = kernel_digest()
-    traffic = MEASURED_TRAFFIC.get((digest, args.mode))
+    traffic = MEASURED_TRAFFIC.get((digest, args.mode, "lds" if in_lds else "hbm"))
 
     extra = None
     if not args.no_extra:
@@ -227,11 +255,11 @@ def main():
                                   cfg["windows"][3], cfg["windows"][5], cfg["windows"][2], seg),
                    "mode": args.mode, "walkers": W, "attempts_timed": attempts,
                    "parallelism": "one wavefront per walker, single GPU"},
-        "roofline": {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / LDS_PEAK_GBS, "traffic": traffic,
+        "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": "GB/s",
+                     "frac": achieved / peak, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch", "kernel_digest": digest,
                      "kernel": "sweep_fast_kernel (%s)" % args.mode,
-                     "bytes_per_attempt": bytes_per_attempt(zsum, args.mode),
+                     "bytes_per_attempt": bpa, "walkers_per_block": lc["walkers_per_block"],
                      "avg_launch_ms": avg_sweep_s * 1e3},
         "cpu_baseline": cpu,
         "extra": extra,
