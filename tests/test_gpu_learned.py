@@ -1,6 +1,6 @@
 """Learned proposal in the REWL walk (FP32_DE mode) through the C ABI.
 
-The uniform proposal is the judge: a walk with the learned proposal must
+The uniform proposal is the reference: a walk with the learned proposal must
 reproduce the oracle's (uniform-proposal) ln g within the same statistical
 bounds, because the exact q-ratio enters the acceptance."""
 import json
