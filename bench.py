@@ -103,8 +103,9 @@ def extra_measurements(torch, workloads, Run):
     """The same kernels on workloads that fill the chip (reported beside the
     headline figure), each with an autotuned launch shape: the 64 uneven
     instances in the persistent kernel, the L=16 eight-shell workload (1024
-    walkers) with the uniform and with the learned proposal, and the L=32
-    workload (1024 walkers, 65,536 spins each)."""
+    walkers) with the uniform and with the learned proposal, the L=32
+    workload (1024 walkers, 65,536 spins each), and the shape of the paper's
+    largest run (L=40, 893 windows x 1 walker, two shells)."""
     import numpy as np
     out = {}
     cfgs = workloads.batched(64)
@@ -124,7 +125,8 @@ def extra_measurements(torch, workloads, Run):
     log("bench: batched %.3e attempts/s" % rate)
     from paper_1411_4212_amd import learned
     for name, wl, kinds in (("L16_8shell", workloads.c4(), ("uniform", "learned")),
-                            ("L32_8shell", workloads.c5(), ("uniform",))):
+                            ("L32_8shell", workloads.c5(), ("uniform",)),
+                            ("L40_paper_shape_893x1", workloads.paper_l40(), ("uniform",))):
         for kind in kinds:
             r = Run([dict(lattice=wl["lattice"], windows=wl["windows"], schedule=wl["schedule"])], mode="fp32_de")
             r.init(wl["seed"], workloads.init_spins(wl))
@@ -133,7 +135,7 @@ def extra_measurements(torch, workloads, Run):
             r.autotune(segments=1)
             lc = r.launch()
             rate, dt = _timed(r, lambda: r.run(2), torch)
-            z = 112
+            z = {2: 14, 4: 50, 8: 112}[len(wl["lattice"][2])]
             out["%s_%s" % (name, kind)] = {
                 "walkers": r.n_walkers, "attempts_per_s": rate, "seconds": dt, "segments": 2, "proposal": kind,
                 "walkers_per_block": lc["walkers_per_block"], "spins_in_lds": lc["spins_in_lds"],

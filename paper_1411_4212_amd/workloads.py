@@ -183,6 +183,20 @@ def c5():
                 schedule=(4, 5, 1.0, 2.0 ** -20, 10000, 100 * N), seed=0, init="ferro")
 
 
+def paper_l40():
+    """The paper's largest run in shape (Sec. results: L = 40, 893 windows at
+    o = 0.75, one walker each): bcc L=40 (128,000 spins) with nearest and
+    next-nearest couplings J = (1, 0.5), the range cut as the paper cuts it,
+    100 bins per window, configurations in HBM; ferromagnetic start."""
+    L, h, m = 40, 893, 1
+    N = 2 * L ** 3
+    J = [1.0, 0.5]
+    Emin, Emax = paper_cut(L, J)
+    return dict(name="bcc_L40_J2_893x1", lattice=("bcc", L, J),
+                windows=(Emin, Emax, _bins_for(h), h, 0.75, m),
+                schedule=(4, 5, 1.0, 2.0 ** -20, 10000, 100 * N), seed=0, init="ferro")
+
+
 def batched(n_instances=64):
     """64 independent runs of uneven size in one context: bcc L in
     {6, 8, 10, 12}, four sign-mixed shells J_n in [-0.2, 1.0), 8..32 windows x
