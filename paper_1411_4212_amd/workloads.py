@@ -138,6 +138,18 @@ def c2(E_range=None):
                 schedule=(4, 5, 1.0, 2.0 ** -20, 10000, 100 * N), seed=0)
 
 
+def c2_l6():
+    """The couplings, bin width (about 2.2 J) and schedule of c2 on a smaller
+    lattice, bcc L=6 (432 spins), 8 windows x 8 walkers: a run that reaches
+    ln f = 2^-20 in minutes (time-to-converge comparisons)."""
+    L = 6
+    N = 2 * L ** 3
+    Emin, Emax = paper_cut(L, J_C2)
+    return dict(name="bcc_L6_J4_8x8", lattice=("bcc", L, list(J_C2)),
+                windows=(Emin, Emax, _bins_for_width((Emin, Emax), 8, 2.22), 8, 0.75, 8),
+                schedule=(4, 5, 1.0, 2.0 ** -20, 10000, 100 * N), seed=0)
+
+
 def _bins_for(h, per_window=100, overlap=0.75):
     """Global bin count that gives `per_window` bins per window."""
     return int(round(per_window * (1 + (h - 1) * (1 - overlap))))
