@@ -103,6 +103,9 @@ def run(cfg, proposal="uniform", cap_s=600.0, rounds=256, harvest_iter=8, harves
             lg_k, vis_k = analysis.combine_walkers([r.lng(0, w) for w in ws], [r.visited(0, w) for w in ws])
             frags["win%03d" % k] = np.where(vis_k, lg_k, np.nan)
     fr = {}
+    m_ = inst["m"]
+    fr["window_done_s"] = [None if np.isnan(done_at[k * m_:(k + 1) * m_]).any()
+                           else round(float(done_at[k * m_:(k + 1) * m_].max()), 1) for k in range(inst["h"])]
     for q in (50, 75, 90, 100):
         k = int(math.ceil(q / 100.0 * r.n_walkers))
         srt = np.sort(done_at)
