@@ -1,0 +1,44 @@
+"""Input recipes (paper_1411_4212_amd/workloads.py): sizes and bin widths
+of the named workloads stay within the library's documented limits and
+follow the readings they state."""
+import math
+
+import pytest
+
+
+def _per_window(c):
+    Emin, Emax, B, h, o, m = c["windows"]
+    return int(math.floor(B / (1 + (h - 1) * (1 - o)) + 0.5))
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c2_l6", "c4", "c5", "paper_l40"])
+def test_workload_limits(name):
+    from paper_1411_4212_amd import workloads
+    c = getattr(workloads, name)()
+    Emin, Emax, B, h, o, m = c["windows"]
+    assert Emin < Emax and B >= h and 1 <= m <= 64
+    assert _per_window(c) <= 4096
+    assert len(c["lattice"][2]) <= 8
+
+
+def test_bin_widths():
+    from paper_1411_4212_amd import workloads as W
+    width = lambda c: (c["windows"][1] - c["windows"][0]) / c["windows"][2]
+    assert abs(width(W.c2()) - 2.22) < 0.01
+    assert abs(width(W.c2_l6()) - 2.22) < 0.01
+    assert abs(width(W.c4()) - 3.0) < 0.01
+    assert abs(width(W.c5()) - 4.0) < 0.01
+    assert _per_window(W.c1()) == 100
+    assert _per_window(W.paper_l40()) == 100 and W.paper_l40()["windows"][3] == 893
+
+
+def test_paper_cut_fractions():
+    """E_min = E_lo + span/28 and E_max = E_lo + 5 span/7 of the quench span."""
+    from paper_1411_4212_amd import workloads as W
+    lo, hi = W.KNOWN_SPANS_L8[tuple(W.J_C2)]
+    Emin, Emax = W.paper_cut(8, W.J_C2)
+    span = hi - lo
+    assert abs(Emin - (lo + span / 28)) < 1e-9 and abs(Emax - (lo + 5 * span / 7)) < 1e-9
+    # extensive scaling to other sizes
+    Emin6, Emax6 = W.paper_cut(6, W.J_C2)
+    assert abs(Emin6 / (2 * 6 ** 3) - Emin / 1024) < 1e-12
