@@ -64,7 +64,6 @@ def hbm_bytes_per_attempt(z, mode):
 def cpu_baseline(cfg, seconds):
     """The oracle as it stands, on the host cores, on a bounded sample:
     whole segments of the same workload until `seconds` have elapsed."""
-    sys.path.insert(0, os.path.join(ROOT, "tests"))
     import oracle
     from oracle.build import build_oracle
     build_oracle()
