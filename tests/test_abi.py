@@ -46,3 +46,20 @@ def test_trace_record_layout():
     import oracle
     assert rewl.TRACE_DTYPE.itemsize == 24
     assert rewl.TRACE_DTYPE == oracle.TRACE_DTYPE
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    """No CPU fallback: importing the binding without librewl.so raises."""
+    import os
+    import shutil
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    pkg = tmp_path / "paper_1411_4212_amd"
+    pkg.mkdir()
+    shutil.copy(os.path.join(root, "paper_1411_4212_amd", "rewl.py"), pkg / "rewl.py")
+    (pkg / "__init__.py").write_text("")
+    r = subprocess.run([sys.executable, "-c", "import paper_1411_4212_amd.rewl"], cwd=str(tmp_path),
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "librewl.so is not built" in r.stderr
