@@ -803,6 +803,8 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
     const double lnf = st.lnf;
     const bool frozen = st.done != 0;
     const bool discovering = (st.iter == 0) && !frozen;
+    const double lnf_add = frozen ? 0.0 : lnf;
+    const uint32_t h_add = frozen ? 0u : 1u;
     // ln g and H of the current bin live in registers while the walker
     // stays in it; LDS holds them again once it leaves and at the end
     double cur = uniform_d(Ld.lng[bin - ilo]);
@@ -935,8 +937,11 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
             }
         }
         wave_sync();
-        const int nvalid = (int)((n_end - n0) < 64 ? (n_end - n0) : 64);
-        const bool trace_b = trace != nullptr && n0 < (uint64_t)a.trace_cap;
+        const int nvalid = __builtin_amdgcn_readfirstlane((int)((n_end - n0) < 64 ? (n_end - n0) : 64));
+        // moves of this batch that go to the trace (uniform)
+        const int ntr = (trace == nullptr || n0 >= (uint64_t)a.trace_cap)
+                            ? 0
+                            : __builtin_amdgcn_readfirstlane((int)((uint64_t)a.trace_cap - n0 < 64 ? (uint64_t)a.trace_cap - n0 : 64));
         for (int p = 0; p < nvalid; p += 4) {
             fields(p);
             bool stale = false;
@@ -1022,11 +1027,12 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
                     for (int q = 0; q < Q; ++q) hit |= (grp > g) && (nidx[q] == site);
                     stale = __builtin_amdgcn_ballot_w64(hit) != 0ull;
                 }
-                if (!frozen) {
-                    cur = cur + lnf;
-                    hcur = hcur + 1u;
-                }
-                if (trace_b && n < (uint64_t)a.trace_cap && lane == 0) {
+                // a finished walker adds +0: every ln g value stays as it is
+                // (a -0 would turn into +0, the same number)
+                cur = cur + lnf_add;
+                hcur = hcur + h_add;
+                if (p + g < ntr) {
+                    // every lane stores the same (uniform) record
                     rewl_trace_rec rec;
                     rec.site = (uint32_t)site;
                     rec.flags = (accept ? 1u : 0u) | (outside ? 2u : 0u);
