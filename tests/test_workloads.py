@@ -42,3 +42,32 @@ def test_paper_cut_fractions():
     # extensive scaling to other sizes
     Emin6, Emax6 = W.paper_cut(6, W.J_C2)
     assert abs(Emin6 / (2 * 6 ** 3) - Emin / 1024) < 1e-12
+
+
+def test_weak_scaling_layout():
+    """Fixed window width and overlap, windows growing with the lattice (Sec.
+    results): the width taken from the L = 40 range and 893 windows gives 893
+    windows at L = 40 and the paper's 11 at L = 10; every layout covers the
+    paper's cut of its range, with 100 bins per window."""
+    from paper_1411_4212_amd import weak_scaling as ws
+    from paper_1411_4212_amd import workloads as W
+    assert ws.layout(10)["h"] == 11
+    assert ws.layout(40)["h"] == 893
+    prev = 0
+    for L in (10, 20, 30, 40, 50):
+        lay = ws.layout(L)
+        lo, hi = W.paper_cut(L, list(ws.J_PAPER_SHAPE))
+        assert lay["E_min"] == lo and lay["E_max"] >= hi - 1e-6
+        # one window fewer would not cover the range
+        W_ = lay["width"]
+        assert W_ * (1 + (lay["h"] - 2) * (1 - ws.OVERLAP)) < hi - lo
+        assert lay["bins"] == round(100 * (1 + (lay["h"] - 1) * (1 - ws.OVERLAP)))
+        assert lay["h"] > prev
+        prev = lay["h"]
+    # the L = 40 layout is the paper-shaped workload's
+    c = W.paper_l40()
+    lay = ws.layout(40)
+    assert (lay["bins"], lay["h"]) == (c["windows"][2], c["windows"][3])
+    assert abs(lay["E_max"] - c["windows"][1]) < 1e-6 * abs(c["windows"][1] - c["windows"][0])
+    s = ws.layout(10, serial=True)
+    assert (s["h"], s["bins"]) == (1, 350)
