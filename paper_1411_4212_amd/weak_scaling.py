@@ -52,6 +52,27 @@ def layout(L, J=J_PAPER_SHAPE, serial=False, bin_width=None):
     return dict(E_min=lo, E_max=lo + span, bins=B, h=h, m=1, width=W)
 
 
+def summarize(first):
+    """Per-window move counts at the first flat histogram (None = not within
+    the cap) -> quantiles over all windows, an unfinished window counting as
+    infinitely slow ("qX": moves by which X % of the windows had finished,
+    None if they had not), and finished windows per tenth of the window
+    index (low to high energy)."""
+    nw = len(first)
+    allm = np.sort(np.array([np.inf if f is None else f for f in first], dtype=float))
+    quant = {}
+    for q in (5, 10, 25, 50, 75, 100):
+        v = float(allm[max(int(math.ceil(q / 100.0 * nw)) - 1, 0)])
+        quant["q%d" % q] = v if np.isfinite(v) else None
+    tenth = [0] * 10
+    for w in range(nw):
+        if first[w] is not None:
+            tenth[min(10 * w // nw, 9)] += 1
+    done = [f for f in first if f is not None]
+    return dict(finished=len(done), walkers=nw, moves_quantiles=quant, finished_per_tenth=tenth,
+                median_of_finished=float(np.median(done)) if done else None)
+
+
 def run_one(L, serial=False, cap_moves=2 * 10 ** 7, seg=10000, poll_segments=10, seed=0,
             J=J_PAPER_SHAPE, bin_width=None):
     """Run REWL (or the serial walk) from the ferromagnet until every window
@@ -87,24 +108,9 @@ def run_one(L, serial=False, cap_moves=2 * 10 ** 7, seg=10000, poll_segments=10,
     seconds = time.perf_counter() - t0
     launch = r.launch()
     r.close()
-    done = [f for f in first if f is not None]
-    # quantiles over all windows, an unfinished window counting as infinitely slow
-    allm = np.array([np.inf if f is None else f for f in first], dtype=float)
-    quant = {}
-    for q in (5, 10, 25, 50, 75, 100):
-        v = float(np.sort(allm)[max(int(math.ceil(q / 100.0 * nw)) - 1, 0)])
-        quant["q%d" % q] = None if not np.isfinite(v) else v
-    # finished windows per tenth of the energy range (window index order)
-    tenth = [0] * 10
-    for w in range(nw):
-        if first[w] is not None:
-            tenth[min(10 * w // nw, 9)] += 1
     return dict(L=L, N=N, serial=serial, windows=lay["h"], bins=lay["bins"],
                 window_width=round(lay["width"], 2), cap_moves=cap_moves,
-                resolution_moves=poll_segments * seg,
-                finished=len(done), walkers=nw, moves_quantiles=quant,
-                finished_per_tenth=tenth,
-                median_of_finished=float(np.median(done)) if done else None,
+                resolution_moves=poll_segments * seg, **summarize(first),
                 seconds=round(seconds, 2), init_seconds=round(t_init, 2),
                 spins_in_lds=bool(launch["spins_in_lds"]))
 

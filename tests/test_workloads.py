@@ -71,3 +71,21 @@ def test_weak_scaling_layout():
     assert abs(lay["E_max"] - c["windows"][1]) < 1e-6 * abs(c["windows"][1] - c["windows"][0])
     s = ws.layout(10, serial=True)
     assert (s["h"], s["bins"]) == (1, 350)
+
+
+def test_weak_scaling_summary():
+    """Quantiles count an unfinished window as infinitely slow; the tenths
+    split the window index range evenly."""
+    from paper_1411_4212_amd.weak_scaling import summarize
+    first = [None, None, 300, 100, 200, 400, 500, 600, 700, 800]
+    s = summarize(first)
+    assert s["finished"] == 8 and s["walkers"] == 10
+    q = s["moves_quantiles"]
+    # sorted: 100 .. 800, inf, inf; qX is the ceil(X % of 10)-th smallest
+    assert q["q10"] == 100 and q["q50"] == 500 and q["q75"] == 800
+    assert q["q100"] is None
+    assert s["finished_per_tenth"] == [0, 0, 1, 1, 1, 1, 1, 1, 1, 1]
+    assert s["median_of_finished"] == 450
+    s = summarize([None] * 3)
+    assert s["finished"] == 0 and s["moves_quantiles"]["q5"] is None and s["median_of_finished"] is None
+    assert summarize([5])["moves_quantiles"]["q100"] == 5
