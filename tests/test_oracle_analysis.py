@@ -3,7 +3,6 @@ against constructions with known answers."""
 import math
 
 import numpy as np
-import pytest
 from scipy import optimize, stats
 
 

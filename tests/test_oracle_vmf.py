@@ -2,7 +2,6 @@
 import math
 
 import numpy as np
-import pytest
 
 from oracle import vmf_mlp as V
 
