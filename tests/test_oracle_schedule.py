@@ -16,6 +16,8 @@ oracle's code:
   and none is taken early; a segment that visits a new bin is not flat;
 - p = 0 makes every segment without a new bin flat.
 """
+import math
+
 import numpy as np
 
 CHAIN = (4, [0, 1, 2], [1, 2, 3], [1.0, 1.0, 1.0])   # open chain, E in [-3, 3]
@@ -140,3 +142,73 @@ def test_p_zero_every_segment_without_new_bins_is_flat(oracle_mod):
         assert snaps[-1][w]["st"]["done"]
         assert quiet_segments == 4
         assert snaps[-1][w]["st"]["iter"] == 3
+
+
+def test_exchange_step_against_its_definition(oracle_mod):
+    """Replica exchange (Sec. parallel scheme), one walker per window so the
+    pairing is fixed: a step of parity t pairs windows (k, k+1) with
+    k = t mod 2.  A pair may swap only when each walker's bin lies in the other
+    window and was visited there; it swaps with probability
+    min(1, g_i(E_X) g_j(E_Y) / (g_i(E_Y) g_j(E_X))); a swap exchanges the
+    configuration, E and bin exactly and leaves every ln g and H alone.
+    Certain swaps (ratio >= 1) must happen, impossible ones must not, and the
+    others must happen at the predicted rate (binomial, 4 sigma)."""
+    N = 12
+    o = oracle_mod.Oracle(explicit=(N, list(range(N - 1)), list(range(1, N)), [1.0] * (N - 1)))
+    o.set_windows(-11.0, 11.0, 120, 3, 0.75, 1)
+    # short segments and a loose flatness bar (p = 0.1): the first iteration
+    # can end before a walker has seen its whole window, so pairs whose bins
+    # lie in the other window but were never visited there occur
+    o.set_schedule(1, 10, 1.0, 2.0 ** -30, 10, 0)
+    o.set_threads(1)
+    o.init(11)
+    wins = [o.window(w) for w in range(3)]
+    certain = impossible = unvisited = 0
+    p_sum = p_var = swaps = 0.0
+    n_prob = 0
+    for _ in range(1500):
+        o.run(1)
+        t = o.step_counter()
+        pre = [o.walker(w) for w in range(3)]
+        lng = [o.lng(w).copy() for w in range(3)]
+        hist = [o.hist(w) for w in range(3)]
+        att0, acc0 = o.exchange_stats()
+        o.exchange()
+        post = [o.walker(w) for w in range(3)]
+        att1, acc1 = o.exchange_stats()
+        for w in range(3):
+            assert np.array_equal(o.lng(w).view(np.uint64), lng[w].view(np.uint64))
+            assert np.array_equal(o.hist(w)[0], hist[w][0])
+        i = t % 2
+        j = i + 1
+        rest = [w for w in range(3) if w not in (i, j)]
+        for w in rest:
+            assert (post[w]["cfg"], post[w]["E"], post[w]["bin"]) == (pre[w]["cfg"], pre[w]["E"], pre[w]["bin"])
+        swapped = post[i]["cfg"] == pre[j]["cfg"]
+        key = lambda s: (s["cfg"], s["E"], s["bin"])
+        if swapped:
+            assert key(post[i]) == key(pre[j]) and key(post[j]) == key(pre[i])
+        else:
+            assert key(post[i]) == key(pre[i]) and key(post[j]) == key(pre[j])
+        assert att1[i] == att0[i] + 1 and acc1[i] == acc0[i] + int(swapped)
+        (li, hi_), (lj, hj) = wins[i], wins[j]
+        a, b = pre[i]["bin"], pre[j]["bin"]
+        in_range = lj <= a < hj and li <= b < hi_
+        feasible = in_range and hist[j][1][a - lj] and hist[i][1][b - li]
+        unvisited += in_range and not feasible
+        if not feasible:
+            impossible += 1
+            assert not swapped
+            continue
+        lnP = (lng[i][a - li] - lng[i][b - li]) + (lng[j][b - lj] - lng[j][a - lj])
+        if lnP >= 0:
+            certain += 1
+            assert swapped
+        else:
+            p = math.exp(lnP)
+            n_prob += 1
+            p_sum += p
+            p_var += p * (1 - p)
+            swaps += swapped
+    assert certain > 100 and impossible > 100 and unvisited > 100 and n_prob > 200
+    assert abs(swaps - p_sum) <= 4 * math.sqrt(p_var) + 1
