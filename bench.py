@@ -29,6 +29,16 @@ MEASURED_TRAFFIC = {
     # profiles/sweep_fast_c2_fp32_counters.md: FETCH 1355.0 KiB x 2.00 + WRITE 2754.5 KiB x 1.00
     ("60a24928d224d1fc", "fp32_de", "lds"): 5595648,
 }
+# Instruction mix of the same launches (SQ counters, one rocprofv3 --pmc pass,
+# per trial move): the second axis next to the bandwidth fraction, since a
+# lone wavefront per walker is bound by its serial issue chain, not by LDS.
+MEASURED_ISSUE = {
+    # profiles/sweep_fast_c2_fp32_counters.md
+    ("60a24928d224d1fc", "fp32_de", "lds"): {"valu_insts_per_attempt": 69.5,
+                                             "salu_insts_per_attempt": 25.7,
+                                             "lds_insts_per_attempt": 5.1,
+                                             "wave_clk_per_attempt": 845},
+}
 KERNEL_SOURCES = ["rewl_kernels.hip", "rewl_device.h", "rewl_internal.h", "rewl_mlp_device.h"]
 
 
@@ -227,6 +237,7 @@ def main():
         log("bench: copy calibration done (3 x 256 MiB)")
     digest = kernel_digest()
     traffic = MEASURED_TRAFFIC.get((digest, args.mode, "lds" if in_lds else "hbm"))
+    issue = MEASURED_ISSUE.get((digest, args.mode, "lds" if in_lds else "hbm"))
 
     extra = None
     if not args.no_extra:
@@ -261,7 +272,7 @@ def main():
                      "traffic_unit": "HBM bytes per launch", "kernel_digest": digest,
                      "kernel": "sweep_fast_kernel (%s)" % args.mode,
                      "bytes_per_attempt": bpa, "walkers_per_block": lc["walkers_per_block"],
-                     "avg_launch_ms": avg_sweep_s * 1e3},
+                     "avg_launch_ms": avg_sweep_s * 1e3, "issue": issue},
         "cpu_baseline": cpu,
         "extra": extra,
     }

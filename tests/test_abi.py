@@ -63,3 +63,16 @@ def test_binding_fails_loudly_without_library(tmp_path):
                        capture_output=True, text=True, timeout=300)
     assert r.returncode != 0
     assert "librewl.so is not built" in r.stderr
+
+
+def test_bench_measured_figures_are_documented():
+    """The traffic and instruction-mix figures bench.py reports are keyed by
+    the digest of the kernel sources they were measured on (a changed kernel
+    reports null until measured again); every such entry must come with the
+    profile summary that documents it."""
+    import bench
+    assert set(bench.MEASURED_TRAFFIC) == set(bench.MEASURED_ISSUE)
+    prof = open(os.path.join(ROOT, "profiles", "sweep_fast_c2_fp32_counters.md")).read()
+    for (digest, mode, res), nbytes in bench.MEASURED_TRAFFIC.items():
+        assert digest in prof and mode == "fp32_de" and res == "lds"
+        assert ("%.3e" % nbytes).replace("e+0", "e") in prof       # e.g. 5.596e6
