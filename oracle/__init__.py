@@ -18,14 +18,17 @@ _lib = None
 
 TRACE_DTYPE = np.dtype([("site", "<u4"), ("flags", "<u4"), ("E", "<f8"),
                         ("bin", "<i4"), ("attempt_lo", "<u4")])
+# drive into the window: flags bit 0 accepted, bit 1 proposal inside the window
+DRIVE_DTYPE = np.dtype([("attempt", "<u4"), ("flags", "<u4"), ("E", "<f8"), ("Eb", "<f8")])
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
+        path = os.environ.get("REWL_ORACLE_LIB", LIB)
+        if path == LIB and not os.path.exists(LIB):
             build_oracle()
-        L = C.CDLL(LIB)
+        L = C.CDLL(path)
         vp, i32, i64, u32, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_double
         P = C.POINTER
         L.orc_philox4x32_10.argtypes = [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]
@@ -75,6 +78,17 @@ def lib():
         L.orc_step_counter.argtypes = [vp]
         L.orc_step_counter.restype = i64
         L.orc_read_trace.argtypes = [vp, i32, vp, i64]
+        L.orc_set_proposal_mlp.argtypes = [vp, P(dbl)]
+        L.orc_mlp_param_count.argtypes = []
+        L.orc_mlp_log_q.argtypes = [P(dbl), P(dbl), P(dbl)]
+        L.orc_mlp_log_q.restype = dbl
+        L.orc_mlp_sample.argtypes = [P(dbl), P(dbl), P(dbl), P(dbl), P(dbl)]
+        L.orc_set_drive_trace.argtypes = [vp, i64]
+        L.orc_read_drive.argtypes = [vp, i32, vp, i64]
+        L.orc_read_drive.restype = i64
+        L.orc_read_round_trips.argtypes = [vp, P(C.c_uint32), i32]
+        L.orc_write_lng.argtypes = [vp, i32, P(dbl), P(C.c_uint8), i32]
+        L.orc_shift_energy.argtypes = [vp, i32, dbl]
         _lib = L
     return _lib
 
@@ -111,6 +125,27 @@ def wl_accept_prob_q(lng_a, lng_b, lnq_old, lnq_new):
 
 def re_accept_prob(lngi_a, lngi_b, lngj_b, lngj_a):
     return lib().orc_re_accept_prob(float(lngi_a), float(lngi_b), float(lngj_b), float(lngj_a))
+
+
+def mlp_log_q(theta, x, s):
+    """ln q(s | x) of the learned proposal with FP64 parameters theta."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    ss = np.ascontiguousarray(s, dtype=np.float64)
+    return lib().orc_mlp_log_q(_p(th, C.c_double), _p(xx, C.c_double), _p(ss, C.c_double))
+
+
+def mlp_sample(theta, x, u, uni):
+    """One draw of the learned proposal for uniforms u = (u_mix, u_w, u_phi)
+    and the direction `uni` used on its uniform branch."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    uu = np.ascontiguousarray(u, dtype=np.float64)
+    un = np.ascontiguousarray(uni, dtype=np.float64)
+    out = np.zeros(3)
+    lib().orc_mlp_sample(_p(th, C.c_double), _p(xx, C.c_double), _p(uu, C.c_double),
+                         _p(un, C.c_double), _p(out, C.c_double))
+    return out
 
 
 def bcc_shells(n_shells):
@@ -206,6 +241,49 @@ class Oracle:
     def set_trace(self, cap):
         lib().orc_set_trace(self._c, cap)
         self.trace_cap = cap
+
+    def set_proposal(self, theta=None):
+        """Learned proposal with FP64 parameters theta (None: uniform)."""
+        if theta is None:
+            lib().orc_set_proposal_mlp(self._c, None)
+            return
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        if th.size != lib().orc_mlp_param_count():
+            raise OracleError("expected %d parameters" % lib().orc_mlp_param_count())
+        lib().orc_set_proposal_mlp(self._c, _p(th, C.c_double))
+
+    def set_drive_trace(self, cap):
+        lib().orc_set_drive_trace(self._c, cap)
+        self.drive_cap = cap
+
+    def drive(self, w):
+        out = np.zeros(self.drive_cap, dtype=DRIVE_DTYPE)
+        n = lib().orc_read_drive(self._c, w, out.ctypes.data_as(C.c_void_p), self.drive_cap)
+        if n < 0:
+            raise OracleError("no drive trace")
+        return out[:n]
+
+    def round_trips(self):
+        out = np.zeros(self.W, dtype=np.uint32)
+        n = lib().orc_read_round_trips(self._c, _p(out, C.c_uint32), self.W)
+        if n < 0:
+            raise OracleError("round trips: %d" % n)
+        return out
+
+    def write_lng(self, w, lng, visited=None):
+        lg = np.ascontiguousarray(lng, dtype=np.float64)
+        if visited is None:
+            st = lib().orc_write_lng(self._c, w, _p(lg, C.c_double), None, lg.size)
+        else:
+            vi = np.ascontiguousarray(visited, dtype=np.uint8)
+            st = lib().orc_write_lng(self._c, w, _p(lg, C.c_double), _p(vi, C.c_uint8), lg.size)
+        if st:
+            raise OracleError("write_lng: %d" % st)
+
+    def shift_energy(self, w, delta):
+        st = lib().orc_shift_energy(self._c, w, float(delta))
+        if st:
+            raise OracleError("shift_energy: %d" % st)
 
     def init(self, seed, init_spins=None):
         if init_spins is not None:

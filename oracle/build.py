@@ -12,16 +12,26 @@ SRC = os.path.join(HERE, "rewl_oracle.c")
 LIB = os.path.join(HERE, "librewl_oracle.so")
 
 
-def build_oracle(force=False):
-    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
-        return LIB
-    tmp = LIB + ".tmp"
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-Wall",
+SAN_LIB = os.path.join(HERE, "librewl_oracle_san.so")
+
+
+def build_oracle(force=False, sanitize=False):
+    """Build the oracle; with sanitize=True an AddressSanitizer +
+    UndefinedBehaviorSanitizer build goes to librewl_oracle_san.so (load it
+    with REWL_ORACLE_LIB set to that path and libasan preloaded)."""
+    lib = SAN_LIB if sanitize else LIB
+    if not force and os.path.exists(lib) and os.path.getmtime(lib) >= os.path.getmtime(SRC):
+        return lib
+    tmp = lib + ".tmp"
+    san = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+           "-fno-omit-frame-pointer", "-g"] if sanitize else []
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-Wall"] + san + [
            "-shared", "-fPIC", "-o", tmp, SRC, "-lm"]
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build_oracle(force=True))
+    import sys
+    print(build_oracle(force=True, sanitize="--sanitize" in sys.argv))

@@ -54,6 +54,7 @@
 #define TAG_EXCH 4u
 #define TAG_PERM 5u
 #define TAG_INIT_CONFIG 6u
+#define TAG_LEARNED 7u
 
 /* ------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw: "Parallel random numbers:
@@ -380,6 +381,16 @@ typedef struct {
     unsigned char *trace;  /* [W][trace_cap] records of 24 bytes */
     int check_energy;      /* test mode: full recompute after every accept */
     double max_check_err;
+    /* learned proposal (NULL: uniform new direction) */
+    double *mlp;           /* [ORC_MLP_PARAMS] FP64 parameters */
+    double hs;             /* largest sum of |J| over a site's neighbours */
+    /* drive into the window: per-attempt records (test mode) */
+    int64_t drive_cap;
+    unsigned char *drive;  /* [W][drive_cap] records of 24 bytes */
+    int64_t *drive_len;    /* [W] */
+    /* replica round trips, per configuration: (half trips << 2) | last
+     * extreme window visited (1 lowest, 2 highest, 0 none yet) */
+    uint32_t *rtrip;
 } octx;
 
 typedef struct {
@@ -437,6 +448,7 @@ static void free_walkers(octx *c)
     c->w = NULL;
     free(c->spins); c->spins = NULL;
     free(c->xatt); free(c->xacc); c->xatt = c->xacc = NULL;
+    free(c->rtrip); c->rtrip = NULL;
 }
 
 void orc_destroy(octx *c)
@@ -444,6 +456,9 @@ void orc_destroy(octx *c)
     if (!c) return;
     free_walkers(c);
     free(c->trace);
+    free(c->drive);
+    free(c->drive_len);
+    free(c->mlp);
     lat_free(&c->lat);
     free(c);
 }
@@ -552,17 +567,181 @@ double orc_re_accept_prob(double lngi_a, double lngi_b, double lngj_b, double ln
 }
 
 /* ------------------------------------------------------------------ */
+/* Learned proposal (an extension; the paper's move is a uniform new    */
+/* direction).  Wang-Landau with an asymmetric proposal q(.|x) whose    */
+/* input x does not involve the moved spin stays exact when the         */
+/* acceptance carries q(S_i|x) / q(S'|x) (the Metropolis-Hastings form  */
+/* of the acceptance of the original WL algorithm).                     */
+/*                                                                      */
+/* x = (h_i / h_s, e_w): the local field (which never contains S_i)     */
+/* scaled by h_s = the largest sum of |J| over a site's neighbours, and */
+/* the walker's window-centre energy per spin in units of h_s / 2.      */
+/* A 4-64-64-12 perceptron with ReLU gives, per component c = 0..2,     */
+/* v_c (3 values) and a logit a_c:  kappa_c = clip(|v_c|, 1e-3, 1e3),   */
+/* mu_c = v_c / |v_c|, alpha = softmax(a), and                          */
+/*   q(s) = eps/(4 pi) + (1 - eps) sum_c alpha_c f(s; mu_c, kappa_c),   */
+/*   f(s; mu, k) = k / (2 pi (1 - e^{-2k})) exp(k (mu.s - 1)),          */
+/* the von Mises-Fisher density on the unit sphere, eps = 0.05.         */
+/* Parameters: W1[64][4], b1[64], W2[64][64], b2[64], W3[12][64], b3[12]. */
+/* ------------------------------------------------------------------ */
+#define ORC_MLP_PARAMS (64 * 4 + 64 + 64 * 64 + 64 + 12 * 64 + 12)
+#define MLP_EPS 0.05
+#define MLP_KMIN 1e-3
+#define MLP_KMAX 1e3
+
+typedef struct {
+    double mu[3][3];
+    double kappa[3];
+    double alpha[3];
+} omix;
+
+static void mlp_forward(const double *th, const double x[4], double out[12])
+{
+    const double *W1 = th, *b1 = W1 + 64 * 4, *W2 = b1 + 64, *b2 = W2 + 64 * 64;
+    const double *W3 = b2 + 64, *b3 = W3 + 12 * 64;
+    double a1[64], a2[64];
+    for (int i = 0; i < 64; ++i) {
+        double z = b1[i];
+        for (int k = 0; k < 4; ++k) z = z + W1[i * 4 + k] * x[k];
+        a1[i] = z > 0.0 ? z : 0.0;
+    }
+    for (int i = 0; i < 64; ++i) {
+        double z = b2[i];
+        for (int k = 0; k < 64; ++k) z = z + W2[i * 64 + k] * a1[k];
+        a2[i] = z > 0.0 ? z : 0.0;
+    }
+    for (int i = 0; i < 12; ++i) {
+        double z = b3[i];
+        for (int k = 0; k < 64; ++k) z = z + W3[i * 64 + k] * a2[k];
+        out[i] = z;
+    }
+}
+
+static void mlp_mixture(const double out[12], omix *m)
+{
+    double amax = out[3];
+    if (out[7] > amax) amax = out[7];
+    if (out[11] > amax) amax = out[11];
+    double e[3], es = 0.0;
+    for (int c = 0; c < 3; ++c) { e[c] = exp(out[4 * c + 3] - amax); es += e[c]; }
+    for (int c = 0; c < 3; ++c) {
+        const double vx = out[4 * c], vy = out[4 * c + 1], vz = out[4 * c + 2];
+        const double r = sqrt(vx * vx + vy * vy + vz * vz);
+        double k = r;
+        if (k < MLP_KMIN) k = MLP_KMIN;
+        if (k > MLP_KMAX) k = MLP_KMAX;
+        m->kappa[c] = k;
+        m->alpha[c] = e[c] / es;
+        if (r > 0.0) {
+            m->mu[c][0] = vx / r; m->mu[c][1] = vy / r; m->mu[c][2] = vz / r;
+        } else {
+            m->mu[c][0] = 0.0; m->mu[c][1] = 0.0; m->mu[c][2] = 1.0;
+        }
+    }
+}
+
+/* ln q(s) of the mixture */
+static double mix_log_q(const omix *m, const double s[3])
+{
+    double t = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        const double k = m->kappa[c];
+        const double w = m->mu[c][0] * s[0] + m->mu[c][1] * s[1] + m->mu[c][2] * s[2];
+        const double lnf = log(k) - log(2.0 * M_PI) - log(-expm1(-2.0 * k)) + k * (w - 1.0);
+        t += m->alpha[c] * exp(lnf);
+    }
+    return log(MLP_EPS / (4.0 * M_PI) + (1.0 - MLP_EPS) * t);
+}
+
+/* One draw from q: with probability eps the given uniform direction, else
+ * a component by its weight, then w = mu.s by inverting the vMF marginal
+ * CDF of w, F(w) = (e^{k(w-1)} - e^{-2k}) / (1 - e^{-2k}), and a uniform
+ * azimuth about mu (two unit vectors orthogonal to mu complete the frame).  */
+static void mix_sample(const omix *m, double u_mix, double u_w, double u_phi, const double uni[3],
+                       double s[3])
+{
+    if (u_mix < MLP_EPS) { s[0] = uni[0]; s[1] = uni[1]; s[2] = uni[2]; return; }
+    const double um = (u_mix - MLP_EPS) / (1.0 - MLP_EPS);
+    int c = 2;
+    if (um < m->alpha[0]) c = 0;
+    else if (um < m->alpha[0] + m->alpha[1]) c = 1;
+    const double k = m->kappa[c];
+    const double *mu = m->mu[c];
+    double w = 1.0 + log(u_w + (1.0 - u_w) * exp(-2.0 * k)) / k;
+    if (w > 1.0) w = 1.0;
+    if (w < -1.0) w = -1.0;
+    /* e1: the coordinate axis least aligned with mu, made orthogonal to it */
+    int ax = 0;
+    if (fabs(mu[1]) < fabs(mu[ax])) ax = 1;
+    if (fabs(mu[2]) < fabs(mu[ax])) ax = 2;
+    double e1[3] = {0.0, 0.0, 0.0};
+    e1[ax] = 1.0;
+    const double d = mu[ax];
+    for (int q = 0; q < 3; ++q) e1[q] -= d * mu[q];
+    const double n1 = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+    for (int q = 0; q < 3; ++q) e1[q] /= n1;
+    const double e2[3] = {mu[1] * e1[2] - mu[2] * e1[1], mu[2] * e1[0] - mu[0] * e1[2],
+                          mu[0] * e1[1] - mu[1] * e1[0]};
+    const double phi = 2.0 * M_PI * u_phi;
+    const double rt = sqrt(1.0 - w * w > 0.0 ? 1.0 - w * w : 0.0);
+    for (int q = 0; q < 3; ++q) s[q] = w * mu[q] + rt * (cos(phi) * e1[q] + sin(phi) * e2[q]);
+}
+
+/* set (or with NULL clear) the learned proposal's parameters */
+int orc_set_proposal_mlp(octx *c, const double *theta)
+{
+    free(c->mlp);
+    c->mlp = NULL;
+    if (!theta) return ORC_OK;
+    c->mlp = (double *)malloc(sizeof(double) * ORC_MLP_PARAMS);
+    memcpy(c->mlp, theta, sizeof(double) * ORC_MLP_PARAMS);
+    return ORC_OK;
+}
+
+int orc_mlp_param_count(void) { return ORC_MLP_PARAMS; }
+
+/* ln q(s | x) and one draw, for tests: x[4], s[3]; u = (u_mix, u_w, u_phi),
+ * uni[3] the direction used on the uniform branch */
+double orc_mlp_log_q(const double *theta, const double x[4], const double s[3])
+{
+    double out[12];
+    omix m;
+    mlp_forward(theta, x, out);
+    mlp_mixture(out, &m);
+    return mix_log_q(&m, s);
+}
+
+void orc_mlp_sample(const double *theta, const double x[4], const double u[3], const double uni[3],
+                    double s[3])
+{
+    double out[12];
+    omix m;
+    mlp_forward(theta, x, out);
+    mlp_mixture(out, &m);
+    mix_sample(&m, u[0], u[1], u[2], uni, s);
+}
+
+/* ------------------------------------------------------------------ */
 /* Walkers.                                                            */
 /* ------------------------------------------------------------------ */
 
 /* Drive a walker from its starting configuration into its window:
  * propose plain moves, accept a move if it lands in the window or strictly
  * closer to it, stop on entry.  Fails after 10^4 N proposals.             */
+typedef struct {
+    uint32_t attempt;
+    uint32_t flags;        /* bit0 accepted, bit1 the proposal lies in the window */
+    double E;              /* energy before the attempt */
+    double Eb;             /* proposed energy */
+} odrive;
+
 static int drive_into_window(octx *c, owalker *w)
 {
     double *S = cfg_spins(c, w->cfg);
     int N = c->lat.N;
     int b;
+    size_t widx = (size_t)(w - c->w);
+    if (c->drive_len) c->drive_len[widx] = 0;
     if (in_window(c, w->E, w->lo, w->hi, &b)) { w->bin = b; return ORC_OK; }
     uint64_t cap = (uint64_t)10000 * (uint64_t)N;
     for (uint64_t n = 0; n < cap; ++n) {
@@ -574,13 +753,43 @@ static int drive_into_window(octx *c, owalker *w)
         local_field(&c->lat, S, i, h);
         double Eb = w->E + delta_e(S + 3 * (size_t)i, sn, h);
         int inside = in_window(c, Eb, w->lo, w->hi, &b);
-        if (inside || window_distance(c, Eb, w->lo, w->hi) < window_distance(c, w->E, w->lo, w->hi)) {
+        int acc = inside || window_distance(c, Eb, w->lo, w->hi) < window_distance(c, w->E, w->lo, w->hi);
+        if (c->drive && n < (uint64_t)c->drive_cap) {
+            odrive *d = (odrive *)(c->drive + (widx * (size_t)c->drive_cap + (size_t)n) * sizeof(odrive));
+            d->attempt = (uint32_t)n;
+            d->flags = (uint32_t)acc | ((uint32_t)inside << 1);
+            d->E = w->E;
+            d->Eb = Eb;
+            c->drive_len[widx] = (int64_t)n + 1;
+        }
+        if (acc) {
             S[3 * (size_t)i] = sn[0]; S[3 * (size_t)i + 1] = sn[1]; S[3 * (size_t)i + 2] = sn[2];
             w->E = Eb;
             if (inside) { w->bin = b; return ORC_OK; }
         }
     }
     return ORC_EINIT;
+}
+
+/* record the first `cap` attempts of each walker's drive into its window at
+ * the next orc_init (test mode; 0 turns it off) */
+int orc_set_drive_trace(octx *c, int64_t cap)
+{
+    free(c->drive);
+    free(c->drive_len);
+    c->drive = NULL;
+    c->drive_len = NULL;
+    c->drive_cap = cap > 0 ? cap : 0;
+    return ORC_OK;
+}
+
+/* walker's drive records: returns how many were written (<= cap) */
+int64_t orc_read_drive(const octx *c, int walker, void *out, int64_t cap)
+{
+    if (!c->drive || walker < 0 || walker >= c->W) return ORC_EINVAL;
+    int64_t n = c->drive_len[walker] < cap ? c->drive_len[walker] : cap;
+    memcpy(out, c->drive + (size_t)walker * (size_t)c->drive_cap * sizeof(odrive), (size_t)n * sizeof(odrive));
+    return n;
 }
 
 int orc_init(octx *c, uint32_t seed, const double *init_spins)
@@ -598,6 +807,22 @@ int orc_init(octx *c, uint32_t seed, const double *init_spins)
     if (c->trace_cap > 0) {
         free(c->trace);
         c->trace = (unsigned char *)calloc((size_t)c->W * (size_t)c->trace_cap, sizeof(otrace));
+    }
+    free(c->drive);
+    free(c->drive_len);
+    c->drive = NULL;
+    c->drive_len = NULL;
+    if (c->drive_cap > 0) {
+        c->drive = (unsigned char *)calloc((size_t)c->W * (size_t)c->drive_cap, sizeof(odrive));
+        c->drive_len = (int64_t *)calloc((size_t)c->W, sizeof(int64_t));
+    }
+    c->rtrip = (uint32_t *)calloc((size_t)c->W, sizeof(uint32_t));
+    /* h_s: the largest sum of |J| over one site's neighbours */
+    c->hs = 0.0;
+    for (int i = 0; i < N; ++i) {
+        double a = 0.0;
+        for (int k = 0; k < c->lat.deg[i]; ++k) a += fabs(c->lat.Jn[(size_t)i * c->lat.zmax + k]);
+        if (a > c->hs) c->hs = a;
     }
     int status = ORC_OK;
     for (int wi = 0; wi < c->W; ++wi) {
@@ -637,7 +862,8 @@ int orc_init(octx *c, uint32_t seed, const double *init_spins)
 
 /* One Wang-Landau trial move of walker w (steps in the order of the
  * original algorithm: propose, evaluate E_B, accept with min(1, g_A/g_B),
- * then multiply g~ and increment H at the current state).               */
+ * times q(S_i|x)/q(S'|x) with the learned proposal, then multiply g~ and
+ * increment H at the current state).                                    */
 static void wl_attempt(octx *c, owalker *w)
 {
     int N = c->lat.N;
@@ -651,34 +877,56 @@ static void wl_attempt(octx *c, owalker *w)
     orc_sphere(c->seed, w->stream, n, TAG_SPHERE, sn);
     local_field(&c->lat, S, i, h);
     double *si = S + 3 * (size_t)i;
+    double lnq_ratio = 0.0;
+    if (c->mlp) {
+        /* x from the field at i (S_i is not part of it), so q(.|x) is the
+         * same before and after the move */
+        const double ec = c->Emin + 0.5 * (double)(w->lo + w->hi) * ((c->Emax - c->Emin) / (double)c->B);
+        double x[4] = {h[0] / c->hs, h[1] / c->hs, h[2] / c->hs, ec / ((double)N * 0.5 * c->hs)};
+        double out[12];
+        omix m;
+        mlp_forward(c->mlp, x, out);
+        mlp_mixture(out, &m);
+        uint32_t ru[4];
+        draw(c->seed, w->stream, n, 0u, TAG_LEARNED, ru);
+        const double u_mix = (double)(ru[0] >> 8) * (1.0 / 16777216.0);
+        const double u_w = ((double)(ru[1] >> 8) + 0.5) * (1.0 / 16777216.0);
+        const double u_phi = (double)(ru[2] >> 8) * (1.0 / 16777216.0);
+        double uni[3] = {sn[0], sn[1], sn[2]};
+        mix_sample(&m, u_mix, u_w, u_phi, uni, sn);
+        lnq_ratio = mix_log_q(&m, si) - mix_log_q(&m, sn);
+    }
     double Eb = w->E + delta_e(si, sn, h);
     int bb;
-    int acc = 0, outside = 0;
+    int acc = 0, outside = 0, newbin = 0;
+    double lnb = 0.0;
     if (in_window(c, Eb, w->lo, w->hi, &bb)) {
-        if (!w->vis[bb - w->lo]) {
-            /* A bin not yet visited.  During the first iteration the walker
-             * discovers its range: the bin's initial guess is taken equal to
-             * the current bin's estimate and the histogram restarts.  After
-             * the first iteration the range is fixed and such proposals are
-             * rejected. */
-            if (w->iter == 0 && !w->done) {
-                w->lng[bb - w->lo] = w->lng[w->bin - w->lo];
-                memset(w->H, 0, sizeof(uint32_t) * (size_t)(w->hi - w->lo));
-            } else {
-                bb = -1;
-                outside = 1;
-                w->oow++;
-            }
+        if (w->vis[bb - w->lo]) {
+            lnb = w->lng[bb - w->lo];
+        } else if (w->iter == 0 && !w->done) {
+            /* A bin not yet visited, during the first iteration: the walker
+             * is still discovering its range.  The bin's initial guess is the
+             * current bin's estimate; it joins the range, and the histogram
+             * restarts, when the walker enters it. */
+            newbin = 1;
+            lnb = w->lng[w->bin - w->lo];
+        } else {
+            /* after the first iteration the range is fixed */
+            outside = 1;
         }
-        if (bb >= 0) {
-            double lr = wl_log_ratio(w->lng[w->bin - w->lo], w->lng[bb - w->lo]);
+        if (!outside) {
+            double lr = wl_log_ratio(w->lng[w->bin - w->lo], lnb) + lnq_ratio;
             acc = metropolis(lr, u);
         }
     } else {
         outside = 1;
-        w->oow++;
     }
+    if (outside) w->oow++;
     if (acc) {
+        if (newbin) {
+            w->lng[bb - w->lo] = lnb;
+            memset(w->H, 0, sizeof(uint32_t) * (size_t)(w->hi - w->lo));
+        }
         si[0] = sn[0]; si[1] = sn[1]; si[2] = sn[2];
         w->E = Eb;
         w->bin = bb;
@@ -784,11 +1032,12 @@ static void exchange_step(octx *c)
             c->xatt[k]++;
             if (!in_window(c, a->E, b->lo, b->hi, &ba_in_b)) continue;
             if (!in_window(c, b->E, a->lo, a->hi, &bb_in_a)) continue;
-            /* each walker's estimate must exist at the energy it receives */
-            if (!b->vis[ba_in_b - b->lo] || !a->vis[bb_in_a - a->lo]) continue;
-            /* the stored bins (which a resync may have clamped) must lie in
-             * the other window too */
+            /* the bins the walkers hold (which a resync may have clamped),
+             * which the swap hands over and the ratio reads, must lie in the
+             * other window, and each walker's estimate must exist at the bin
+             * it receives */
             if (a->bin < b->lo || a->bin >= b->hi || b->bin < a->lo || b->bin >= a->hi) continue;
+            if (!b->vis[a->bin - b->lo] || !a->vis[b->bin - a->lo]) continue;
             uint32_t rr[4];
             draw(c->seed, c->instance, t, ((uint32_t)k << 16) | (uint32_t)r, TAG_EXCH, rr);
             double u = u53(rr[0], rr[1]);
@@ -802,6 +1051,23 @@ static void exchange_step(octx *c)
         }
     }
     free(perm);
+    /* Replica diffusion (the round trips of Fig. 1 of the results): a
+     * configuration now held by a walker of the lowest window whose last
+     * extreme window was the highest one (or the reverse) has made one more
+     * half trip. */
+    if (c->h >= 2) {
+        for (int e = 0; e < 2; ++e) {
+            const int win = e == 0 ? 0 : c->h - 1;
+            const uint32_t ext = e == 0 ? 1u : 2u;
+            for (int r = 0; r < m; ++r) {
+                uint32_t *v = &c->rtrip[c->w[win * m + r].cfg];
+                uint32_t last = *v & 3u, trips = *v >> 2;
+                if (last == ext) continue;
+                if (last != 0u) trips += 1u;
+                *v = (trips << 2) | ext;
+            }
+        }
+    }
 }
 
 int orc_all_done(const octx *c)
@@ -907,4 +1173,40 @@ int orc_read_trace(const octx *c, int walker, void *out, int64_t cap)
     int64_t n = cap < c->trace_cap ? cap : c->trace_cap;
     memcpy(out, c->trace + (size_t)walker * (size_t)c->trace_cap * sizeof(otrace), (size_t)n * sizeof(otrace));
     return (int)n;
+}
+
+/* half trips per configuration (see the exchange step) */
+int orc_read_round_trips(const octx *c, uint32_t *out, int cap)
+{
+    if (!c->rtrip) return ORC_ESTATE;
+    for (int i = 0; i < c->W && i < cap; ++i) out[i] = c->rtrip[i] >> 2;
+    return c->W;
+}
+
+/* Replace a walker's ln g~ (and its visited bins, NULL = all) over its
+ * window, e.g. to run with fixed weights; the bins count as seen by the
+ * flatness test's new-bin rule. */
+int orc_write_lng(octx *c, int walker, const double *lng, const uint8_t *vis, int cap)
+{
+    if (!c->inited || walker < 0 || walker >= c->W || !lng) return ORC_EINVAL;
+    owalker *w = &c->w[walker];
+    int nb = w->hi - w->lo;
+    int nvis = 0;
+    for (int j = 0; j < nb && j < cap; ++j) {
+        w->lng[j] = lng[j];
+        w->vis[j] = vis ? (vis[j] != 0) : 1;
+    }
+    w->vis[w->bin - w->lo] = 1;
+    for (int j = 0; j < nb; ++j) nvis += w->vis[j];
+    w->nvis_prev = nvis;
+    return ORC_OK;
+}
+
+/* Test mode: add `delta` to a walker's running energy, as an accumulated
+ * rounding drift would; the next resync must undo it. */
+int orc_shift_energy(octx *c, int walker, double delta)
+{
+    if (!c->inited || walker < 0 || walker >= c->W) return ORC_EINVAL;
+    c->w[walker].E += delta;
+    return ORC_OK;
 }

@@ -426,30 +426,35 @@ __global__ void __launch_bounds__(256) sweep_kernel(KArgs a)
         const double xb = (Eb - Emin) * inv;
         int bb = -1;
         bool outside = true;
+        bool newbin = false;
+        double lnb = 0.0;
         if (xb >= lo && xb < hi) {
             bb = (int)floor(xb);
             outside = false;
-            if (!L.vis[bb - ilo]) {
-                // first entry into a bin: during the first iteration its
-                // initial guess is the current bin's estimate and H restarts;
+            if (L.vis[bb - ilo]) {
+                lnb = L.lng[bb - ilo];
+            } else if (discovering) {
+                // a bin not visited yet, during the first iteration: its
+                // initial guess is the current bin's estimate; it joins the
+                // range (and H restarts) when the walker enters it
+                newbin = true;
+                lnb = cur;
+            } else {
                 // afterwards the range is fixed
-                if (discovering) {
-                    L.lng[bb - ilo] = cur;
-                    for (int j = lane; j < nb; j += kWave) L.H[j] = 0u;
-                } else {
-                    bb = -1;
-                    outside = true;
-                }
+                bb = -1;
+                outside = true;
             }
         }
         bool accept = false;
-        double lnb = 0.0;
         if (bb >= 0) {
-            lnb = L.lng[bb - ilo];
             const double lr = cur - lnb;
             accept = (lr >= 0.0) || (u < exp_det(lr));
         }
         oow += outside ? 1u : 0u;
+        if (accept && newbin) {
+            L.lng[bb - ilo] = lnb;
+            for (int j = lane; j < nb; j += kWave) L.H[j] = 0u;
+        }
         if (accept) {
             V v;
             v.x = nx;
@@ -581,13 +586,11 @@ __device__ void exchange_instance(const KArgs &a, int ii, uint64_t t)
             const double xb = (Eb - I.Emin) * I.inv_de;
             bool ok = (xa >= (double)db.lo && xa < (double)db.hi) && (xb >= (double)da.lo && xb < (double)da.hi);
             const int bina = sa->bin, binb = sb->bin;
-            if (ok) {
-                const int ba = (int)floor(xa), bbn = (int)floor(xb);
-                ok = a.vis[db.bin_off + (ba - db.lo)] && a.vis[da.bin_off + (bbn - da.lo)];
-                // stored bins (a resync may have clamped them) must lie in
-                // the other window as well
-                ok = ok && !(bina < db.lo || bina >= db.hi || binb < da.lo || binb >= da.hi);
-            }
+            // the stored bins (the ones the swap installs and the ratio
+            // reads) must lie in the other window, on a bin the receiving
+            // walker has visited
+            ok = ok && !(bina < db.lo || bina >= db.hi || binb < da.lo || binb >= da.hi);
+            if (ok) ok = a.vis[db.bin_off + (bina - db.lo)] && a.vis[da.bin_off + (binb - da.lo)];
             if (ok) {
                 const U4 rr = draw(a.seed, (uint32_t)ii, t, ((uint32_t)k << 16) | (uint32_t)r, TAG_EXCH);
                 const double u = u53(rr.x, rr.y);
@@ -981,14 +984,15 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
                 double lnb = same ? cur : lnb_m;
                 uint32_t hb = same ? hcur : hb_m;
                 bool outside = !inwin;
+                bool newbin = false;
                 if (inwin && __builtin_isnan(lnb)) {
-                    // a bin not visited yet
+                    // a bin not visited yet: during the first iteration its
+                    // initial guess is the current bin's estimate, and it
+                    // joins the range when the walker enters it; afterwards
+                    // the range is fixed
                     if (discovering) {
                         lnb = cur;
-                        Ld.lng[bb - ilo] = cur;
-                        for (int j = lane; j < nb; j += kWave) Ld.H[j] = 0u;
-                        hb = 0u;
-                        hcur = 0u;
+                        newbin = true;
                     } else {
                         outside = true;
                     }
@@ -998,6 +1002,13 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
                 const double lr = LEARNED ? (cur - lnb) + lnqr : (cur - lnb);
                 const bool accept = !outside && (lnu < lr);
                 oow += outside ? 1u : 0u;
+                if (accept && newbin) {
+                    // the range grew: the histogram restarts (the new bin's
+                    // ln g rides in `cur` until the walker leaves it)
+                    for (int j = lane; j < nb; j += kWave) Ld.H[j] = 0u;
+                    hb = 0u;
+                    hcur = 0u;
+                }
                 if (accept && bb != bin) {
                     // leave the current bin: its ln g and H back to LDS
                     Ld.lng[bin - ilo] = cur;
@@ -1017,6 +1028,9 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
                     } else {
                         if (lane == 16 * g) S[site] = mv_prop;
                     }
+                    // one lane stored the spin; other lanes of this wavefront
+                    // gather it for later moves
+                    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
                     E = Eb;
                     bin = bb;
                     cur = lnb;
