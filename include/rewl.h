@@ -262,9 +262,10 @@ rewl_status rewl_read_visited(rewl_ctx *ctx, int32_t inst, int32_t walker, uint8
 rewl_status rewl_read_walker_state(rewl_ctx *ctx, int32_t inst, int32_t walker,
                                    rewl_walker_state *out);
 /* Overwrite a walker's ln g~ (and visited flags; NULL = all visited) for its
- * window, min(cap, hi - lo) entries from `lng` (host).  With ln f ~ 0 and a
- * flatness fraction of 1 this runs a fixed-weight (multicanonical) walk;
- * it also restores a saved estimate.  Synchronises the stream. */
+ * window, min(cap, hi - lo) entries from `lng` (host); a bin marked not
+ * visited holds the initial guess ln g~ = 0.  With ln f ~ 0 and a flatness
+ * fraction of 1 this runs a fixed-weight (multicanonical) walk; it also
+ * restores a saved estimate.  Synchronises the stream. */
 rewl_status rewl_write_lng(rewl_ctx *ctx, int32_t inst, int32_t walker, const double *lng,
                            const uint8_t *visited, int32_t cap);
 
@@ -331,6 +332,7 @@ rewl_status rewl_mlp_loss_grad(const float *dev_records, int64_t n, const float 
 rewl_status rewl_mlp_train(const float *dev_records, int64_t n, int32_t epochs, int32_t batch,
                            float lr, uint64_t seed, float *dev_params, void *dev_workspace,
                            float *loss_per_epoch, void *hip_stream);
+
 
 /* Proposal of a context: kind 0 = uniform direction, 1 = learned (FP32
  * parameters on the device, packed into the context).  FP32_DE mode, bcc

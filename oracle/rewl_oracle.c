@@ -905,11 +905,11 @@ static void wl_attempt(octx *c, owalker *w)
             lnb = w->lng[bb - w->lo];
         } else if (w->iter == 0 && !w->done) {
             /* A bin not yet visited, during the first iteration: the walker
-             * is still discovering its range.  The bin's initial guess is the
-             * current bin's estimate; it joins the range, and the histogram
-             * restarts, when the walker enters it. */
+             * is still discovering its range.  The bin still holds the
+             * initial guess g~ = 1 (ln g~ = 0); it joins the range, and the
+             * histogram restarts, when the walker enters it. */
             newbin = 1;
-            lnb = w->lng[w->bin - w->lo];
+            lnb = w->lng[bb - w->lo];
         } else {
             /* after the first iteration the range is fixed */
             outside = 1;
@@ -923,10 +923,7 @@ static void wl_attempt(octx *c, owalker *w)
     }
     if (outside) w->oow++;
     if (acc) {
-        if (newbin) {
-            w->lng[bb - w->lo] = lnb;
-            memset(w->H, 0, sizeof(uint32_t) * (size_t)(w->hi - w->lo));
-        }
+        if (newbin) memset(w->H, 0, sizeof(uint32_t) * (size_t)(w->hi - w->lo));
         si[0] = sn[0]; si[1] = sn[1]; si[2] = sn[2];
         w->E = Eb;
         w->bin = bb;
@@ -1185,7 +1182,8 @@ int orc_read_round_trips(const octx *c, uint32_t *out, int cap)
 
 /* Replace a walker's ln g~ (and its visited bins, NULL = all) over its
  * window, e.g. to run with fixed weights; the bins count as seen by the
- * flatness test's new-bin rule. */
+ * flatness test's new-bin rule.  A bin marked not visited holds the initial
+ * guess ln g~ = 0. */
 int orc_write_lng(octx *c, int walker, const double *lng, const uint8_t *vis, int cap)
 {
     if (!c->inited || walker < 0 || walker >= c->W || !lng) return ORC_EINVAL;
@@ -1193,8 +1191,8 @@ int orc_write_lng(octx *c, int walker, const double *lng, const uint8_t *vis, in
     int nb = w->hi - w->lo;
     int nvis = 0;
     for (int j = 0; j < nb && j < cap; ++j) {
-        w->lng[j] = lng[j];
         w->vis[j] = vis ? (vis[j] != 0) : 1;
+        w->lng[j] = w->vis[j] ? lng[j] : 0.0;
     }
     w->vis[w->bin - w->lo] = 1;
     for (int j = 0; j < nb; ++j) nvis += w->vis[j];

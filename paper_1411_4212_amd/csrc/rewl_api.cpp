@@ -886,7 +886,11 @@ rewl_status rewl_write_lng(rewl_ctx *ctx, int32_t inst, int32_t walker, const do
         if (!std::isfinite(lng[j])) return fail(REWL_EINVAL, "non-finite ln g");
     std::vector<uint8_t> vis(n, 1);
     if (visited) vis.assign(visited, visited + n);
-    HIP_TRY(hipMemcpy((double *)ctx->buf[REWL_BUF_LNG] + wd.bin_off, lng, sizeof(double) * n, hipMemcpyHostToDevice));
+    // a bin marked not visited holds the initial guess ln g~ = 0
+    std::vector<double> val(lng, lng + n);
+    for (int32_t j = 0; j < n; ++j)
+        if (!vis[j]) val[j] = 0.0;
+    HIP_TRY(hipMemcpy((double *)ctx->buf[REWL_BUF_LNG] + wd.bin_off, val.data(), sizeof(double) * n, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy((uint8_t *)ctx->buf[REWL_BUF_VISITED] + wd.bin_off, vis.data(), n, hipMemcpyHostToDevice));
     return REWL_OK;
 }

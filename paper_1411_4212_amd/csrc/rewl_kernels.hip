@@ -434,11 +434,11 @@ __global__ void __launch_bounds__(256) sweep_kernel(KArgs a)
             if (L.vis[bb - ilo]) {
                 lnb = L.lng[bb - ilo];
             } else if (discovering) {
-                // a bin not visited yet, during the first iteration: its
-                // initial guess is the current bin's estimate; it joins the
+                // a bin not visited yet, during the first iteration: it
+                // still holds the initial guess ln g~ = 0; it joins the
                 // range (and H restarts) when the walker enters it
                 newbin = true;
-                lnb = cur;
+                lnb = L.lng[bb - ilo];
             } else {
                 // afterwards the range is fixed
                 bb = -1;
@@ -452,7 +452,6 @@ __global__ void __launch_bounds__(256) sweep_kernel(KArgs a)
         }
         oow += outside ? 1u : 0u;
         if (accept && newbin) {
-            L.lng[bb - ilo] = lnb;
             for (int j = lane; j < nb; j += kWave) L.H[j] = 0u;
         }
         if (accept) {
@@ -986,12 +985,12 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
                 bool outside = !inwin;
                 bool newbin = false;
                 if (inwin && __builtin_isnan(lnb)) {
-                    // a bin not visited yet: during the first iteration its
-                    // initial guess is the current bin's estimate, and it
-                    // joins the range when the walker enters it; afterwards
-                    // the range is fixed
+                    // a bin not visited yet: during the first iteration it
+                    // holds the initial guess ln g~ = 0 and joins the range
+                    // when the walker enters it; afterwards the range is
+                    // fixed
                     if (discovering) {
-                        lnb = cur;
+                        lnb = 0.0;
                         newbin = true;
                     } else {
                         outside = true;
@@ -1004,7 +1003,7 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
                 oow += outside ? 1u : 0u;
                 if (accept && newbin) {
                     // the range grew: the histogram restarts (the new bin's
-                    // ln g rides in `cur` until the walker leaves it)
+                    // ln g~ rides in `cur` until the walker leaves it)
                     for (int j = lane; j < nb; j += kWave) Ld.H[j] = 0u;
                     hb = 0u;
                     hcur = 0u;

@@ -69,10 +69,13 @@ def test_bench_measured_figures_are_documented():
     """The traffic and instruction-mix figures bench.py reports are keyed by
     the digest of the kernel sources they were measured on (a changed kernel
     reports null until measured again); every such entry must come with the
-    profile summary that documents it."""
+    profile summary under profiles/ that documents it (its digest and its
+    scaled byte count)."""
+    import glob
     import bench
     assert set(bench.MEASURED_TRAFFIC) == set(bench.MEASURED_ISSUE)
-    prof = open(os.path.join(ROOT, "profiles", "sweep_fast_c2_fp32_counters.md")).read()
-    for (digest, mode, res), nbytes in bench.MEASURED_TRAFFIC.items():
-        assert digest in prof and mode == "fp32_de" and res == "lds"
-        assert ("%.3e" % nbytes).replace("e+0", "e") in prof       # e.g. 5.596e6
+    docs = [open(p).read() for p in glob.glob(os.path.join(ROOT, "profiles", "*.md"))]
+    for (digest, workload, res), nbytes in bench.MEASURED_TRAFFIC.items():
+        assert res in ("lds", "hbm")
+        mark = ("%.3e" % nbytes).replace("e+0", "e")          # e.g. 5.596e6
+        assert any(digest in d and mark in d for d in docs), (digest, workload, mark)

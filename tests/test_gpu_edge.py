@@ -189,3 +189,21 @@ def test_round_trips_match_host_count():
     _say("half trips", dev.tolist())
     assert np.array_equal(dev.astype(np.int64), half)
     assert half.sum() > 0
+
+
+def test_round_trips_det_equal_oracle():
+    """Deterministic FP64 mode: the device's half-trip count per
+    configuration equals the oracle's, bit for bit, after 300 segments with
+    an exchange step each (same Philox seed, so the same swaps)."""
+    from helpers import oracle_from
+    cfg = dict(lattice=("bcc", 4, [1.0, 0.5]), windows=(-560.0, 160.0, 60, 4, 0.75, 2),
+               schedule=(4, 5, 1.0, 2.0 ** -6, 1500, 0), seed=21)
+    o = oracle_from(cfg)
+    o.run(300)
+    g = gpu_from(cfg, "fp64_det")
+    g.run(300)
+    dev = g.round_trips(0).astype(np.int64)
+    ref = o.round_trips().astype(np.int64)
+    _say("half trips det", dev.tolist(), ref.tolist())
+    assert np.array_equal(dev, ref)
+    assert ref.sum() >= 4

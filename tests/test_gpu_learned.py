@@ -1,8 +1,24 @@
 """Learned proposal in the REWL walk (FP32_DE mode) through the C ABI.
 
 The uniform proposal is the reference: a walk with the learned proposal must
-reproduce the oracle's (uniform-proposal) ln g within the same statistical
-bounds, because the exact q-ratio enters the acceptance."""
+reproduce the oracle's ln g, because the exact q-ratio enters the
+acceptance.  Two oracle references per workload (tests/golden, written by
+make_reference.py from the CPU oracle only):
+
+* the Wang-Landau estimator's mean over many oracle runs (uniform proposal),
+  with its run-to-run spread;
+* for the range that reaches down towards the ordered state, ln g from a
+  fixed-weight oracle run, which carries no Wang-Landau modification error.
+
+Workloads: bcc L=4, J = (1, 0.5), 2 windows x 8 walkers, on the middle of
+the spectrum [-400, -100) (30 bins) and on [-550, -50) (40 bins), whose
+lowest bins lie at 4.3 J per spin against the ferromagnet's 5.5.
+
+Bars (the paper's accuracy check compares Delta with sigma over independent
+runs, Sec. results and discussion): every bin within 5 combined standard
+errors; |Delta| <= 0.02 on every bin whose combined standard error is at
+most 0.004 (where 0.02 is five of them); the specific-heat peak within 0.5%.
+"""
 import json
 import os
 import sys
@@ -13,7 +29,9 @@ import pytest
 from helpers import gpu_from
 
 pytestmark = pytest.mark.gpu
-REF = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "ref_parity_L4.json")
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+REF = {"L4_mid": "ref_parity_L4.json", "L4_low": "ref_parity_L4_low.json"}
+TRUTH = {"L4_low": "truth_L4_low.json"}
 
 
 def _say(*a):
@@ -21,8 +39,12 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _workload(seed=77):
-    wl = json.load(open(REF))["workload"]
+def _ref(name):
+    return json.load(open(os.path.join(GOLD, REF[name])))
+
+
+def _workload(name, seed=77):
+    wl = _ref(name)["workload"]
     return dict(lattice=tuple(wl["lattice"]), windows=tuple(wl["windows"]),
                 schedule=tuple(wl["schedule"]), seed=seed)
 
@@ -43,10 +65,70 @@ def _harvest_and_train(cfg, segments_skip=60, segments_harvest=30, epochs=6):
     return params, recs
 
 
+def _wl_runs(cfg, runs, params=None, tag=""):
+    """`runs` independent instances to convergence; per run the joined,
+    normalised ln g, and the acceptance of every walker."""
+    from oracle.analysis import combine_walkers, join_windows, normalise
+    g = gpu_from([cfg] * runs, "fp32_de")
+    if params is not None:
+        g.set_proposal(params)
+    seg = 0
+    while seg < 20000:
+        g.run(64)
+        seg += 64
+        done = g.poll()
+        if seg % 256 == 0 or done:
+            _say("%s: %d segments%s" % (tag, seg, " (all done)" if done else ""))
+        if done:
+            break
+    assert g.poll()
+    h, m = cfg["windows"][3], cfg["windows"][5]
+    out, acc = [], []
+    for inst in range(runs):
+        frags = []
+        for k in range(h):
+            ws = range(k * m, (k + 1) * m)
+            lo, hi = g.window(inst, k * m)
+            lg, vis = combine_walkers([g.lng(inst, w) for w in ws], [g.visited(inst, w) for w in ws])
+            frags.append((lo, hi, lg, vis))
+        _, lg, _ = join_windows(frags)
+        out.append(normalise(lg))
+        for w in range(h * m):
+            st = g.walker(inst, w)
+            acc.append(st["accepts"] / st["attempts"])
+    return np.array(out), float(np.mean(acc))
+
+
+def _check(tag, cfg, mean_g, se_g, mean_r, se_r):
+    from oracle.analysis import cv_peak, normalise
+    ok = np.isfinite(mean_g) & np.isfinite(mean_r)
+    assert ok.sum() >= 0.9 * len(mean_r)
+    dg, dr = normalise(mean_g, ok), normalise(mean_r, ok)
+    delta = dg - dr
+    se = np.sqrt(se_g ** 2 + se_r ** 2)
+    z = np.abs(delta[ok]) / se[ok]
+    tight = ok & (se <= 0.004)
+    np.set_printoptions(precision=3, suppress=True, linewidth=200)
+    _say(tag, "delta", delta[ok])
+    _say(tag, "z    ", z)
+    _say("%s: max|delta| %.4f (bins with se <= 0.004: %d, max|delta| there %.4f) max z %.2f"
+         % (tag, np.nanmax(np.abs(delta[ok])), tight.sum(),
+            np.abs(delta[tight]).max() if tight.any() else 0.0, z.max()))
+    assert z.max() <= 5.0
+    if tight.any():
+        assert np.abs(delta[tight]).max() <= 0.02
+    Emin, Emax, B = cfg["windows"][:3]
+    Ec = Emin + (np.arange(B) + 0.5) * (Emax - Emin) / B
+    tg, tr = cv_peak(Ec[ok], dg[ok], 1.0, 8.0)[0], cv_peak(Ec[ok], dr[ok], 1.0, 8.0)[0]
+    _say("%s: C_V peak %.4f vs %.4f" % (tag, tg, tr))
+    assert abs(tg - tr) / tr <= 0.005
+    return np.nanmax(np.abs(delta[ok]))
+
+
 def test_harvest_records():
     """Records: one every k-th move, unit spins, |h / h_s| <= 1, and the
     window feature e_w = centre energy / (N h_s / 2) of the walker's window."""
-    cfg = _workload()
+    cfg = _workload("L4_mid")
     g = gpu_from(cfg, "fp32_de")
     g.set_harvest(60000, 10)
     g.run(2)
@@ -67,74 +149,100 @@ def test_harvest_records():
         assert np.allclose(r[:, 3], ec / (N * hs / 2), rtol=1e-6)
 
 
-def test_learned_walk_statistical_parity_and_gain():
-    """Train on records of the plain walk, then run 128 independent learned
-    walks: their mean normalised ln g matches the oracle reference within
-    0.02 and 5 standard errors per bin, the specific-heat peak within 0.5%,
-    and the acceptance rate exceeds the uniform proposal's."""
-    from oracle.analysis import combine_walkers, cv_peak, join_windows, normalise
-    ref = json.load(open(REF))
-    cfg = _workload()
+@pytest.mark.parametrize("name", ["L4_mid", "L4_low"])
+def test_learned_walk_statistical_parity(name):
+    """Train on records of the plain walk, then run 256 independent learned
+    walks: their mean normalised ln g matches the oracle's Wang-Landau mean
+    (and, on the low range, the fixed-weight truth) within the bars above;
+    the learned proposal accepts more often than the uniform one, both
+    measured over whole runs to convergence on the same schedule (uniform
+    walks on these ranges are held to the parity bars in
+    test_gpu_statistical)."""
+    ref = _ref(name)
+    cfg = _workload(name)
     params, _ = _harvest_and_train(cfg)
-    RUNS = 256
-    g = gpu_from([cfg] * RUNS, "fp32_de")
-    g.set_proposal(params)
-    g.run_to_convergence(max_segments=20000, chunk=64)
-    assert g.poll()
-    h, m = cfg["windows"][3], cfg["windows"][5]
-    runs = []
-    acc_l = []
-    for inst in range(RUNS):
-        frags = []
-        for k in range(h):
-            ws = range(k * m, (k + 1) * m)
-            lo, hi = g.window(inst, k * m)
-            lg, vis = combine_walkers([g.lng(inst, w) for w in ws], [g.visited(inst, w) for w in ws])
-            frags.append((lo, hi, lg, vis))
-        _, lg, _ = join_windows(frags)
-        runs.append(normalise(lg))
-        for w in range(h * m):
-            st = g.walker(inst, w)
-            acc_l.append(st["accepts"] / st["attempts"])
-    A = np.array(runs)
-    mean_g = np.nanmean(A, axis=0)
+    A, acc_l = _wl_runs(cfg, 256, params, "learned " + name)
+    _, acc_u = _wl_runs(cfg, 32, None, "uniform " + name)
     mean_r = np.array(ref["mean_lng"])
-    ok = np.isfinite(mean_g) & np.isfinite(mean_r)
-    dg, dr = normalise(mean_g, ok), normalise(mean_r, ok)
-    delta = dg - dr
-    se = np.sqrt(np.nanstd(A, axis=0, ddof=1) ** 2 / RUNS + np.array(ref["std_lng"]) ** 2 / ref["runs"])
-    z = np.abs(delta[ok]) / se[ok]
-    np.set_printoptions(precision=3, suppress=True, linewidth=200)
-    _say("delta", delta[ok])
-    _say("z    ", z)
-    _say("se   ", se[ok])
-    _say("learned: max|delta| %.4f max z %.2f" % (np.nanmax(np.abs(delta[ok])), z.max()))
-    assert np.nanmax(np.abs(delta[ok])) <= 0.02
-    assert z.max() <= 5.0
-    Emin, Emax, B = cfg["windows"][:3]
-    Ec = Emin + (np.arange(B) + 0.5) * (Emax - Emin) / B
-    tg, tr = cv_peak(Ec[ok], dg[ok], 1.0, 8.0)[0], cv_peak(Ec[ok], dr[ok], 1.0, 8.0)[0]
-    _say("C_V peak learned %.4f oracle %.4f" % (tg, tr))
-    assert abs(tg - tr) / tr <= 0.005
-    # acceptance of the plain walk on the same workload
-    p = gpu_from([cfg] * 8, "fp32_de")
-    p.run(40)
-    acc_p = [p.walker(i, w)["accepts"] / p.walker(i, w)["attempts"] for i in range(8) for w in range(h * m)]
-    _say("acceptance learned %.3f plain %.3f" % (np.mean(acc_l), np.mean(acc_p)))
-    assert np.mean(acc_l) > np.mean(acc_p)
+    se_r = np.array(ref["std_lng"]) / np.sqrt(ref["runs"])
+    mean_g = np.nanmean(A, axis=0)
+    se_g = np.nanstd(A, axis=0, ddof=1) / np.sqrt(np.isfinite(A).sum(0))
+    _check("%s learned vs oracle WL" % name, cfg, mean_g, se_g, mean_r, se_r)
+    if name in TRUTH:
+        t = json.load(open(os.path.join(GOLD, TRUTH[name])))
+        _check("%s learned vs truth" % name, cfg, mean_g, se_g, np.array(t["lng"]), np.array(t["se"]))
+    _say("acceptance learned %.3f uniform %.3f (same schedule, to convergence)" % (acc_l, acc_u))
+    assert acc_l > acc_u
+
+
+def _fixed_weight_lng(cfg, W, params, R, segments):
+    """ln g from fixed-weight walks of R instances (ln f = 1e-300, flatness
+    1: the weights never change, H only accumulates): per instance and
+    window, W + ln H over the walkers' summed histogram, windows joined by
+    the mean offset over shared bins."""
+    from oracle.analysis import normalise
+    fixed = dict(cfg, schedule=(1, 1, 1e-300, 1e-300, cfg["schedule"][4], cfg["schedule"][5]))
+    h, m, B = cfg["windows"][3], cfg["windows"][5], cfg["windows"][2]
+    g = gpu_from([fixed] * R, "fp32_de")
+    for i in range(R):
+        for w in range(h * m):
+            lo, hi = g.window(i, w)
+            g.write_lng(i, w, W[lo:hi])
+    if params is not None:
+        g.set_proposal(params)
+    g.run(segments)
+    out = []
+    for i in range(R):
+        acc = np.zeros(B)
+        cnt = np.zeros(B)
+        for k in range(h):
+            lo, hi = g.window(i, k * m)
+            Hs = sum(g.hist(i, w).astype(np.float64) for w in range(k * m, (k + 1) * m))
+            lg = np.where(Hs > 0, W[lo:hi] + np.log(np.maximum(Hs, 1.0)), np.nan)
+            idx = np.arange(lo, hi)
+            have = cnt[idx] > 0
+            okk = np.isfinite(lg)
+            both = have & okk
+            off = np.mean(acc[idx][both] / cnt[idx][both] - lg[both]) if both.any() else 0.0
+            acc[idx[okk]] += lg[okk] + off
+            cnt[idx[okk]] += 1
+        est = np.full(B, np.nan)
+        est[cnt > 0] = acc[cnt > 0] / cnt[cnt > 0]
+        out.append(normalise(est))
+    return np.array(out)
+
+
+def test_learned_fixed_weight_walk_matches_truth():
+    """Fixed-weight (multicanonical) walks on the low range with the oracle
+    truth's weights: the stationary histogram gives ln g = ln g~ + ln H with
+    no Wang-Landau modification error, so this isolates the Markov kernel.
+    Both the learned and the uniform proposal must reproduce the oracle's
+    fixed-weight ln g within 5 standard errors per bin (and 0.02 where the
+    errors allow)."""
+    t = json.load(open(os.path.join(GOLD, TRUTH["L4_low"])))
+    W = np.array(t["weights"])
+    cfg = _workload("L4_low")
+    params, _ = _harvest_and_train(cfg, segments_skip=40, segments_harvest=10, epochs=3)
+    R = 32
+    for kind, p in (("uniform", None), ("learned", params)):
+        X = _fixed_weight_lng(cfg, W, p, R, 60)
+        mean_g = np.nanmean(X, axis=0)
+        se_g = np.nanstd(X, axis=0, ddof=1) / np.sqrt(np.isfinite(X).sum(0))
+        _check("fixed-weight %s vs truth" % kind, cfg, mean_g, se_g, np.array(t["lng"]),
+               np.array(t["se"]))
 
 
 def test_learned_fixed_weight_walk_unbiased():
-    """Fixed-weight (multicanonical) walk: every walker's ln g~ is set to the
-    oracle's reference ln g (ln f = 1e-300, flatness fraction 1, so the
+    """Fixed-weight walk on the middle range: every walker's ln g~ is set to
+    the oracle's reference ln g (ln f = 1e-300, flatness fraction 1, so the
     weights never change and H is never reset); the stationary histogram is
     then H(E) ~ g(E) / g~(E).  The residual ln H of walks with the learned
     proposal (any q, through the exact q-ratio) must equal that of the
     uniform proposal bin by bin: z <= 5 from the spread over 32 independent
     instances, and |mean difference| <= 0.03."""
-    ref = json.load(open(REF))
+    ref = _ref("L4_mid")
     mean_r = np.array(ref["mean_lng"])
-    cfg = _workload()
+    cfg = _workload("L4_mid")
     params, _ = _harvest_and_train(cfg, segments_skip=40, segments_harvest=10, epochs=3)
     fixed = dict(cfg, schedule=(1, 1, 1e-300, 1e-300, cfg["schedule"][4], cfg["schedule"][5]))
     R = 32

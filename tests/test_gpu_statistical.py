@@ -1,14 +1,20 @@
 """Statistical parity of the fast GPU modes with the FP64 oracle.
 
-Reference: tests/golden/ref_parity_L4.json, written by
-tests/golden/make_reference.py from many independent oracle runs of one
-small workload.  Here the same workload runs as many independent instances
-in one GPU context (distinct Philox streams), and the mean normalised
-joined ln g is compared with the oracle's mean:
-  * max |Delta ln g| <= 0.02 over all bins (each mean normalised to zero);
-  * every bin's Delta within 5 standard errors of the two means (the
-    paper's Delta-versus-sigma accuracy check over independent runs);
+References (tests/golden, written by make_reference.py from the CPU oracle
+only): the oracle's mean normalised joined ln g over many independent runs
+of a small workload, and, for the range that reaches down towards the
+ordered state, ln g from a fixed-weight oracle run (no Wang-Landau
+modification error).  Here the same workload runs as many independent
+instances in one GPU context (distinct Philox streams), and the mean
+normalised joined ln g is compared with the references:
+  * every bin's Delta within 5 combined standard errors (the paper's
+    Delta-versus-sigma accuracy check over independent runs);
+  * |Delta| <= 0.02 on every bin whose combined standard error is at most
+    0.004 (where the statistics resolve 0.02; the lowest bins of the low
+    range scatter by 0.1-0.3 per run);
   * the specific-heat peak temperature of the two means within 0.5%.
+Workloads: bcc L=4, J = (1, 0.5), 2 windows x 8 walkers, on [-400, -100)
+(30 bins) and on [-550, -50) (40 bins).
 """
 import json
 import os
@@ -20,7 +26,9 @@ import pytest
 from helpers import gpu_from
 
 pytestmark = pytest.mark.gpu
-REF = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "ref_parity_L4.json")
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+REF = {"L4_mid": "ref_parity_L4.json", "L4_low": "ref_parity_L4_low.json"}
+TRUTH = {"L4_low": "truth_L4_low.json"}
 RUNS = 256
 
 
@@ -29,16 +37,50 @@ def _say(*a):
     sys.stdout.flush()
 
 
+def _check(tag, cfg, mean_g, se_g, mean_r, se_r):
+    from oracle.analysis import cv_peak, normalise
+    ok = np.isfinite(mean_g) & np.isfinite(mean_r)
+    assert ok.sum() >= 0.9 * len(mean_r)
+    dg, dr = normalise(mean_g, ok), normalise(mean_r, ok)
+    delta = dg - dr
+    se = np.sqrt(se_g ** 2 + se_r ** 2)
+    z = np.abs(delta[ok]) / se[ok]
+    tight = ok & (se <= 0.004)
+    np.set_printoptions(precision=3, suppress=True, linewidth=200)
+    _say(tag, "delta", delta[ok])
+    _say(tag, "z    ", z)
+    _say("%s: max|delta| %.4f (bins with se <= 0.004: %d, max|delta| there %.4f) max z %.2f"
+         % (tag, np.nanmax(np.abs(delta[ok])), tight.sum(),
+            np.abs(delta[tight]).max() if tight.any() else 0.0, z.max()))
+    assert z.max() <= 5.0
+    if tight.any():
+        assert np.abs(delta[tight]).max() <= 0.02
+    Emin, Emax, B = cfg["windows"][:3]
+    Ec = Emin + (np.arange(B) + 0.5) * (Emax - Emin) / B
+    tg, tr = cv_peak(Ec[ok], dg[ok], 1.0, 8.0)[0], cv_peak(Ec[ok], dr[ok], 1.0, 8.0)[0]
+    _say("%s: C_V peak %.4f vs %.4f" % (tag, tg, tr))
+    assert abs(tg - tr) / tr <= 0.005
+
+
+@pytest.mark.parametrize("name", ["L4_mid", "L4_low"])
 @pytest.mark.parametrize("mode", ["fp32_de", "fp64"])
-def test_statistical_parity_L4(mode):
-    from oracle.analysis import combine_walkers, cv_peak, join_windows, normalise
-    ref = json.load(open(REF))
+def test_statistical_parity_L4(mode, name):
+    from oracle.analysis import combine_walkers, join_windows, normalise
+    ref = json.load(open(os.path.join(GOLD, REF[name])))
     wl = ref["workload"]
     cfg = dict(lattice=tuple(wl["lattice"]), windows=tuple(wl["windows"]),
                schedule=tuple(wl["schedule"]), seed=77)
-    _say("statistical parity", mode, RUNS, "instances")
+    _say("statistical parity", name, mode, RUNS, "instances")
     g = gpu_from([cfg] * RUNS, mode)
-    g.run_to_convergence(max_segments=20000, chunk=64)
+    seg = 0
+    while seg < 20000:
+        g.run(64)
+        seg += 64
+        done = g.poll()
+        if seg % 256 == 0 or done:
+            _say("%s %s: %d segments%s" % (name, mode, seg, " (all done)" if done else ""))
+        if done:
+            break
     assert g.poll()
     h, m = cfg["windows"][3], cfg["windows"][5]
     runs = []
@@ -53,24 +95,9 @@ def test_statistical_parity_L4(mode):
         runs.append(normalise(lg))
     A = np.array(runs)
     mean_g = np.nanmean(A, axis=0)
-    mean_r = np.array(ref["mean_lng"])
-    ok = np.isfinite(mean_g) & np.isfinite(mean_r)
-    assert ok.sum() >= 0.9 * len(mean_r)
-    dg = normalise(mean_g, ok)
-    dr = normalise(mean_r, ok)
-    delta = dg - dr
-    se = np.sqrt(np.nanstd(A, axis=0, ddof=1) ** 2 / RUNS + np.array(ref["std_lng"]) ** 2 / ref["runs"])
-    z = np.abs(delta[ok]) / se[ok]
-    np.set_printoptions(precision=3, suppress=True, linewidth=200)
-    _say("delta", delta[ok])
-    _say("z    ", z)
-    _say("se   ", se[ok])
-    _say("max|delta| %.4f  max z %.2f" % (np.nanmax(np.abs(delta[ok])), z.max()))
-    assert np.nanmax(np.abs(delta[ok])) <= 0.02
-    assert z.max() <= 5.0
-    Emin, Emax, B = cfg["windows"][:3]
-    Ec = Emin + (np.arange(B) + 0.5) * (Emax - Emin) / B
-    tg = cv_peak(Ec[ok], dg[ok], 1.0, 8.0)[0]
-    tr = cv_peak(Ec[ok], dr[ok], 1.0, 8.0)[0]
-    _say("C_V peak gpu %.4f oracle %.4f" % (tg, tr))
-    assert abs(tg - tr) / tr <= 0.005
+    se_g = np.nanstd(A, axis=0, ddof=1) / np.sqrt(np.isfinite(A).sum(0))
+    _check("%s %s vs oracle WL" % (name, mode), cfg, mean_g, se_g, np.array(ref["mean_lng"]),
+           np.array(ref["std_lng"]) / np.sqrt(ref["runs"]))
+    if name in TRUTH:
+        t = json.load(open(os.path.join(GOLD, TRUTH[name])))
+        _check("%s %s vs truth" % (name, mode), cfg, mean_g, se_g, np.array(t["lng"]), np.array(t["se"]))

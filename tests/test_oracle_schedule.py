@@ -156,17 +156,18 @@ def test_exchange_step_against_its_definition(oracle_mod):
     N = 12
     o = oracle_mod.Oracle(explicit=(N, list(range(N - 1)), list(range(1, N)), [1.0] * (N - 1)))
     o.set_windows(-11.0, 11.0, 120, 3, 0.75, 1)
-    # short segments and a loose flatness bar (p = 0.1): the first iteration
-    # can end before a walker has seen its whole window, so pairs whose bins
-    # lie in the other window but were never visited there occur
-    o.set_schedule(1, 10, 1.0, 2.0 ** -30, 10, 0)
+    # short segments and no flatness bar (p = 0): the first iteration ends at
+    # the first segment that finds no new bin, before a walker has seen its
+    # whole window, so pairs whose bins lie in the other window but were
+    # never visited there occur
+    o.set_schedule(0, 10, 1.0, 2.0 ** -30, 10, 0)
     o.set_threads(1)
     o.init(11)
     wins = [o.window(w) for w in range(3)]
     certain = impossible = unvisited = 0
     p_sum = p_var = swaps = 0.0
     n_prob = 0
-    for _ in range(1500):
+    for _ in range(3000):
         o.run(1)
         t = o.step_counter()
         pre = [o.walker(w) for w in range(3)]
@@ -210,5 +211,5 @@ def test_exchange_step_against_its_definition(oracle_mod):
             p_sum += p
             p_var += p * (1 - p)
             swaps += swapped
-    assert certain > 100 and impossible > 100 and unvisited > 100 and n_prob > 200
+    assert certain > 50 and impossible > 100 and unvisited > 100 and n_prob > 200
     assert abs(swaps - p_sum) <= 4 * math.sqrt(p_var) + 1
