@@ -115,6 +115,76 @@ def run(cfg, proposal="uniform", cap_s=600.0, rounds=256, harvest_iter=8, harves
     return res, bins, lng, frags
 
 
+def race(cfg, proposal="uniform", R=64, chunk=8, cap_s=600.0, harvest_iter=6, harvest_segments=2,
+         harvest_every=4, epochs=4, seed=11, log=None):
+    """R independent REWL runs of one workload in one context, run to the
+    end by the persistent kernel; the wall-clock time at which each run's
+    last walker finished its final ln f iteration (the paper's stopping
+    rule: f has reached f_min), and each run's joined ln g.
+
+    With proposal="learned" the runs start with the uniform proposal; once
+    the median walker has reached ln f <= 2^-harvest_iter, (x, S_i) of every
+    harvest_every-th move is recorded for harvest_segments segments, the
+    network is trained on the device, and the runs continue with the learned
+    proposal.  Harvest and training are inside the measured time."""
+    import torch
+    from . import analysis, learned, workloads
+    from .rewl import Run, rewl_set_harvest
+    r = Run([dict(lattice=cfg["lattice"], windows=cfg["windows"], schedule=cfg["schedule"])] * R,
+            mode="fp32_de")
+    init = workloads.init_spins(cfg)
+    r.init(seed, None if init is None else np.concatenate([init] * R))
+    dev = torch.device("cuda", 0)
+    nw = r.inst[0]["h"] * r.inst[0]["m"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    phase = "plain" if proposal == "learned" else proposal
+    done_at = np.full(R, np.nan)
+    info = {}
+    rounds = 0
+    while True:
+        r.run_persistent(chunk)
+        rounds += chunk
+        all_done = bool(r.poll())
+        el = time.perf_counter() - t0
+        st = [[r.walker(i, w) for w in range(nw)] for i in range(R)]
+        for i in range(R):
+            if np.isnan(done_at[i]) and all(s["done"] for s in st[i]):
+                done_at[i] = el
+        if log:
+            log("%s: %d rounds, %.1f s, %d of %d runs done" % (proposal, rounds, el, np.isfinite(done_at).sum(), R))
+        if all_done or el > cap_s:
+            break
+        its = np.array([s["iteration"] for row in st for s in row])
+        if proposal == "learned" and phase == "plain" and np.median(its) >= harvest_iter:
+            th = time.perf_counter()
+            seg = cfg["schedule"][4]
+            r.set_harvest(harvest_segments * seg // harvest_every + 1, harvest_every)
+            r.run(harvest_segments)
+            recs = r.harvested()
+            rewl_set_harvest(r.ctx, None, 0, 1)
+            params = learned.init_params(1, dev)
+            losses = learned.train(recs, params, epochs=epochs, batch=4096, lr=2e-3, seed=3)
+            r.set_proposal(params)
+            torch.cuda.synchronize()
+            info = dict(records=int(recs.shape[0]), loss=[round(float(x), 4) for x in losses],
+                        harvest_train_s=round(time.perf_counter() - th, 2), switched_at_s=round(el, 2))
+            del recs
+            r.harvest_buf = None
+            phase = "learned"
+    lngs = []
+    for i in range(R):
+        try:
+            lngs.append(analysis.run_lng(r, i)[1])
+        except ValueError:
+            lngs.append(np.full(cfg["windows"][2], np.nan))
+    att = sum(s["attempts"] for row in st for s in row)
+    acc = sum(s["accepts"] for row in st for s in row)
+    r.close()
+    return dict(proposal=proposal, runs=R, done_at=done_at, seconds=time.perf_counter() - t0,
+                acceptance=acc / max(att, 1), attempts=int(att), **info), np.array(lngs)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="c4")

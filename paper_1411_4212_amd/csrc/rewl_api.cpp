@@ -183,6 +183,7 @@ KArgs make_args(rewl_ctx *c)
     a.harvest_cap = c->harvest_cap;
     a.harvest_every = c->harvest_every;
     a.lds_bins = c->lds_bins;
+    a.lds_bin_bytes = c->spins_in_lds ? 13 : 8;
     a.fast_q = c->fast_q;
     a.all_pow2 = c->all_pow2;
     return a;
@@ -193,7 +194,9 @@ KArgs make_args(rewl_ctx *c)
 // fit in 160 KB, otherwise in place in HBM (fast kernel only).
 rewl_status plan_launch(rewl_ctx *c)
 {
-    const size_t bins = ((size_t)c->lds_bins * 13u + 15) & ~(size_t)15;
+    // spins in LDS: spins, ln g, H and visited flags (13 B per bin); spins
+    // in HBM (fast kernel): ln g only (8 B per bin), H stays in HBM
+    const size_t bins = ((size_t)c->lds_bins * 8u + 15) & ~(size_t)15;
     const size_t batch = 64 * 64;
     const size_t with_spins = (((size_t)c->lds_spins_bytes + (size_t)c->lds_bins * 13u + 15) & ~(size_t)15) + batch;
     const size_t without = bins + batch;

@@ -108,6 +108,7 @@ struct KArgs {
     int32_t walkers_per_block;
     int32_t lds_spins_bytes;   // bytes of LDS for spins per walker slot
     int32_t lds_bins;          // window bins per walker slot in LDS
+    int32_t lds_bin_bytes;     // LDS bytes per bin: 13 (ln g, H, visited) or 8 (ln g only)
     int32_t fast_q;            // >0: fast sweep kernel with this many neighbour slots per lane
     int32_t all_pow2;          // every instance has L a power of two
     int32_t spins_in_lds;      // 1: configurations staged in LDS; 0: read in place from HBM

