@@ -333,6 +333,18 @@ rewl_status rewl_mlp_train(const float *dev_records, int64_t n, int32_t epochs, 
                            float lr, uint64_t seed, float *dev_params, void *dev_workspace,
                            float *loss_per_epoch, void *hip_stream);
 
+/* rewl_mlp_train without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  The workspace is a file-scope
+ * device array of the library, one per GPU (2.8 MB, minibatches of at most
+ * 8192 records; a larger batch returns REWL_ERANGE); the calling thread's
+ * current device is used, and hip_stream must belong to it.  The call
+ * allocates nothing.  Calls that overlap on one GPU share that array and
+ * race: serialise them (one stream, or synchronise between calls).  The
+ * results equal rewl_mlp_train's bit for bit. */
+rewl_status rewl_mlp_train_static(const float *dev_records, int64_t n, int32_t epochs, int32_t batch,
+                                  float lr, uint64_t seed, float *dev_params, float *loss_per_epoch,
+                                  void *hip_stream);
 
 /* Proposal of a context: kind 0 = uniform direction, 1 = learned (FP32
  * parameters on the device, packed into the context).  FP32_DE mode, bcc

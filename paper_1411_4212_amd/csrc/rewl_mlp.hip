@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -285,7 +286,7 @@ using namespace rewl::mlp;
 
 namespace {
 rewl_status mfail(rewl_status c, const char *m) { return rewl::report_error(c, m); }
-size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // workspace: m, v, grad (kParams each), loss slot, partials, loss partials
 struct Ws {
@@ -309,7 +310,7 @@ Ws carve(void *w, int nblocks)
     s.lossp = (float *)(p + o);
     return s;
 }
-size_t ws_bytes(int nblocks)
+constexpr size_t ws_bytes(int nblocks)
 {
     return al256(sizeof(float) * kParams) * 3 + 256 + al256(sizeof(float) * kParams * (size_t)nblocks) +
            al256(sizeof(float) * (size_t)nblocks);
@@ -325,6 +326,33 @@ rewl_status grad_step(const float *rec, int64_t n, int32_t count, int32_t random
     hipLaunchKernelGGL(mlp_reduce_kernel, dim3((kParams + 255) / 256), dim3(256), 0, s, w.partial, nblocks,
                        grad_out, w.lossp, add_loss ? w.loss : nullptr);
     return hipGetLastError() == hipSuccess ? REWL_OK : mfail(REWL_EDEVICE, "mlp kernel launch failed");
+}
+// Workspace of rewl_mlp_train_static: a file-scope device array, one copy per
+// GPU, sized for minibatches of up to kStaticMaxBatch records.  Host code
+// never uses the array's name as an address: each device's address comes
+// from hipGetSymbolAddress, taken once per device with that device current.
+constexpr int kStaticMaxBatch = 8192;
+constexpr size_t kStaticScratchBytes = ws_bytes((kStaticMaxBatch + kTB - 1) / kTB);
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+rewl_status static_scratch(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return mfail(REWL_EDEVICE, "no current device");
+    if (dev >= kMaxDevices) return mfail(REWL_EUNSUPPORTED, "device index beyond the static workspace table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+            return mfail(REWL_EDEVICE, "hipGetSymbolAddress of the static workspace failed");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return REWL_OK;
 }
 }  // namespace
 
@@ -425,6 +453,18 @@ rewl_status rewl_mlp_train(const float *dev_records, int64_t n, int32_t epochs, 
     }
     if (hipGetLastError() != hipSuccess) return mfail(REWL_EDEVICE, "training launch failed");
     return REWL_OK;
+}
+
+rewl_status rewl_mlp_train_static(const float *dev_records, int64_t n, int32_t epochs, int32_t batch, float lr,
+                                  uint64_t seed, float *dev_params, float *loss_per_epoch, void *hip_stream)
+{
+    if (batch > kStaticMaxBatch) return mfail(REWL_ERANGE, "batch above 8192 records, the static workspace's limit");
+    void *ws = nullptr;
+    rewl_status st = static_scratch(&ws);
+    if (st) return st;
+    // Adam moments and the loss slot are cleared by fill kernels inside the
+    // call; the gradient partials are overwritten before they are read
+    return rewl_mlp_train(dev_records, n, epochs, batch, lr, seed, dev_params, ws, loss_per_epoch, hip_stream);
 }
 
 }  // extern "C"

@@ -97,6 +97,7 @@ _SIGS = {
     "rewl_mlp_eval": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp],
     "rewl_mlp_loss_grad": [_vp, _i64, _vp, _vp, _P(C.c_double), _vp, _vp],
     "rewl_mlp_train": [_vp, _i64, _i32, _i32, C.c_float, _u64, _vp, _vp, _P(C.c_float), _vp],
+    "rewl_mlp_train_static": [_vp, _i64, _i32, _i32, C.c_float, _u64, _vp, _P(C.c_float), _vp],
     "rewl_get_launch": [_vp, _P(_i32), _P(_i32), _P(_i64)],
     "rewl_total_attempts": [_vp, _P(_u64), _P(_u64)],
 }
@@ -366,6 +367,13 @@ def rewl_mlp_train(dev_records, n, epochs, batch, lr, seed, dev_params, dev_work
     losses = np.zeros(max(epochs, 1), dtype=np.float32)
     _call("rewl_mlp_train", _vp(dev_records), n, epochs, batch, lr, seed, _vp(dev_params),
           _vp(dev_workspace), losses.ctypes.data_as(_P(C.c_float)), _vp(stream))
+    return losses[:epochs]
+
+
+def rewl_mlp_train_static(dev_records, n, epochs, batch, lr, seed, dev_params, stream=0):
+    losses = np.zeros(max(epochs, 1), dtype=np.float32)
+    _call("rewl_mlp_train_static", _vp(dev_records), n, epochs, batch, lr, seed, _vp(dev_params),
+          losses.ctypes.data_as(_P(C.c_float)), _vp(stream))
     return losses[:epochs]
 
 
