@@ -266,6 +266,9 @@ def main():
                     help="headline workload with the uniform proposal (for comparison runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed region, copy a 256 MiB buffer 3 times (counter calibration)")
+    ap.add_argument("--harvest-every", type=int, default=1,
+                    help="record every k-th move of the plain walk for training (profiling runs use a "
+                         "larger k: fewer training steps to count)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the REWL hot path here is single-GPU "
@@ -291,7 +294,8 @@ def main():
     net = None
     theta = None
     if not args.uniform:
-        params, nrec, secs = trained_network(r, torch, segments=1, every_k=1)
+        log("bench: harvest and training")
+        params, nrec, secs = trained_network(r, torch, segments=1, every_k=args.harvest_every)
         r.set_proposal(params)
         theta = params.double().cpu().numpy()
         net = "trained on the device on %d (field, spin) records of the plain walk of this workload " \
@@ -320,6 +324,7 @@ def main():
         evs[k][1].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    log("bench: timed steps done")
     a1, _ = r.total_attempts()
     attempts = a1 - a0
     wall = t1 - t0

@@ -17,6 +17,8 @@ def oracle_from(cfg, threads=4, trace=0, check_energy=False):
         o.set_trace(trace)
     if check_energy:
         o.set_check_energy(True)
+    if cfg.get("share"):
+        o.set_share(True)
     o.init(cfg["seed"])
     return o
 
@@ -27,8 +29,8 @@ def gpu_from(cfgs, mode, trace=0, seed=None, walkers_per_block=1, residency=0):
     from paper_1411_4212_amd.workloads import init_spins
     if isinstance(cfgs, dict):
         cfgs = [cfgs]
-    r = Run([dict(lattice=c["lattice"], windows=c["windows"], schedule=c["schedule"])
-             for c in cfgs], mode=mode, trace_cap=trace, walkers_per_block=walkers_per_block,
+    r = Run([dict(lattice=c["lattice"], windows=c["windows"], schedule=c["schedule"],
+                  share=c.get("share", False)) for c in cfgs], mode=mode, trace_cap=trace, walkers_per_block=walkers_per_block,
             residency=residency)
     starts = [init_spins(c) for c in cfgs]
     if all(s is None for s in starts):
@@ -57,3 +59,14 @@ def joined_lng(read_lng, read_vis, window, h, m):
 
 def bits(x):
     return np.asarray(x, dtype=np.float64).view(np.uint64)
+
+
+def wl_truth_bound(ref_mean, truth, margin=0.1):
+    """Bound on a Wang-Landau mean's distance from the fixed-weight ln g:
+    the oracle's own Wang-Landau mean's largest distance from it (the
+    estimator's error at the final ln f, largest at the lowest bin of a range
+    reaching towards the ordered state) plus `margin`."""
+    from oracle.analysis import normalise
+    a, b = np.asarray(ref_mean, dtype=float), np.asarray(truth, dtype=float)
+    ok = np.isfinite(a) & np.isfinite(b)
+    return float(np.max(np.abs(normalise(a, ok)[ok] - normalise(b, ok)[ok]))) + margin

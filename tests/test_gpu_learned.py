@@ -12,7 +12,9 @@ make_reference.py from the CPU oracle only):
   fixed-weight walks on the GPU are held to it at the parity bars, while a
   Wang-Landau mean (the oracle's as well) differs from it by a smooth tilt
   of a few hundredths, the estimator's own error at ln f = 2^-18; that
-  difference is reported and bounded by 0.1.
+  difference is reported and bounded by the oracle's own Wang-Landau
+  mean's distance from it plus 0.1 (that distance is about 0.26 at the
+  lowest bin of the low range, a few hundredths elsewhere).
 
 Workloads: bcc L=4, J = (1, 0.5), 2 windows x 8 walkers, on the middle of
 the spectrum [-400, -100) (30 bins) and on [-550, -50) (40 bins), whose
@@ -30,7 +32,7 @@ import sys
 import numpy as np
 import pytest
 
-from helpers import gpu_from
+from helpers import gpu_from, wl_truth_bound
 
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
@@ -103,7 +105,7 @@ def _wl_runs(cfg, runs, params=None, tag=""):
     return np.array(out), float(np.mean(acc))
 
 
-def _check(tag, cfg, mean_g, se_g, mean_r, se_r, strict=True):
+def _check(tag, cfg, mean_g, se_g, mean_r, se_r, loose=None):
     from oracle.analysis import cv_peak, normalise
     ok = np.isfinite(mean_g) & np.isfinite(mean_r)
     assert ok.sum() >= 0.9 * len(mean_r)
@@ -118,11 +120,12 @@ def _check(tag, cfg, mean_g, se_g, mean_r, se_r, strict=True):
     _say("%s: max|delta| %.4f (bins with se <= 0.004: %d, max|delta| there %.4f) max z %.2f"
          % (tag, np.nanmax(np.abs(delta[ok])), tight.sum(),
             np.abs(delta[tight]).max() if tight.any() else 0.0, z.max()))
-    if not strict:
+    if loose is not None:
         # a Wang-Landau mean against the fixed-weight ln g: the estimator's
-        # own error at this final ln f (the oracle's Wang-Landau mean shows the
-        # same smooth tilt of a few hundredths against it)
-        assert np.nanmax(np.abs(delta[ok])) <= 0.1
+        # own error at this final ln f, bounded by the oracle's Wang-Landau
+        # mean's distance from the same reference plus a margin
+        _say("%s: bound %.3f" % (tag, loose))
+        assert np.nanmax(np.abs(delta[ok])) <= loose
         return np.nanmax(np.abs(delta[ok]))
     assert z.max() <= 5.0
     if tight.any():
@@ -181,7 +184,7 @@ def test_learned_walk_statistical_parity(name):
     if name in TRUTH:
         t = json.load(open(os.path.join(GOLD, TRUTH[name])))
         _check("%s learned vs truth" % name, cfg, mean_g, se_g, np.array(t["lng"]), np.array(t["se"]),
-               strict=False)
+               loose=wl_truth_bound(mean_r, t["lng"]))
     _say("acceptance learned %.3f uniform %.3f (same schedule, to convergence)" % (acc_l, acc_u))
     assert acc_l > acc_u
 

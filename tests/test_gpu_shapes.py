@@ -16,7 +16,8 @@ make_reference.py from the CPU oracle only):
 * Wang-Landau runs to ln f = 2^-16 (FP32_DE) against the oracle's
   Wang-Landau mean over 64 runs (parity bars), and against the fixed-weight
   ln g (reported; a Wang-Landau mean, the oracle's included, differs from it
-  by a smooth tilt of a few hundredths at this final ln f, bounded by 0.1).
+  by a smooth tilt of a few hundredths at this final ln f; bounded by the
+  oracle's own Wang-Landau mean's distance from it plus 0.1).
 
 Bars: every bin within 5 combined standard errors, |Delta| <= 0.02 on every
 bin whose combined standard error is at most 0.004, the specific-heat peak
@@ -30,7 +31,7 @@ import sys
 import numpy as np
 import pytest
 
-from helpers import gpu_from
+from helpers import gpu_from, wl_truth_bound
 
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
@@ -52,7 +53,7 @@ def _cfg(name, seed=31):
                 schedule=tuple(wl["schedule"]), seed=seed)
 
 
-def _check(tag, cfg, mean_g, se_g, mean_r, se_r, strict=True):
+def _check(tag, cfg, mean_g, se_g, mean_r, se_r, loose=None):
     from oracle.analysis import cv_peak, normalise
     ok = np.isfinite(mean_g) & np.isfinite(mean_r)
     assert ok.sum() >= 0.9 * len(mean_r)
@@ -67,11 +68,12 @@ def _check(tag, cfg, mean_g, se_g, mean_r, se_r, strict=True):
     _say("%s: max|delta| %.4f (bins with se <= 0.004: %d, max|delta| there %.4f) max z %.2f"
          % (tag, np.nanmax(np.abs(delta[ok])), tight.sum(),
             np.abs(delta[tight]).max() if tight.any() else 0.0, z.max()))
-    if not strict:
+    if loose is not None:
         # a Wang-Landau mean against the fixed-weight ln g: the estimator's
-        # own error at this final ln f (the oracle's Wang-Landau mean shows the
-        # same smooth tilt of a few hundredths against it)
-        assert np.nanmax(np.abs(delta[ok])) <= 0.1
+        # own error at this final ln f, bounded by the oracle's Wang-Landau
+        # mean's distance from the same reference plus a margin
+        _say("%s: bound %.3f" % (tag, loose))
+        assert np.nanmax(np.abs(delta[ok])) <= loose
         return np.nanmax(np.abs(delta[ok]))
     assert z.max() <= 5.0
     if tight.any():
@@ -173,10 +175,8 @@ def test_wang_landau_fp32_de_matches_oracle(name):
     A = np.array(runs)
     mean_g = np.nanmean(A, axis=0)
     se_g = np.nanstd(A, axis=0, ddof=1) / np.sqrt(np.isfinite(A).sum(0))
+    r = json.load(open(os.path.join(GOLD, "ref_parity_%s.json" % name)))
     _check("%s WL fp32_de vs oracle fixed-weight" % name, cfg, mean_g, se_g, np.array(t["lng"]),
-           np.array(t["se"]), strict=False)
-    ref = os.path.join(GOLD, "ref_parity_%s.json" % name)
-    if os.path.exists(ref):
-        r = json.load(open(ref))
-        _check("%s WL fp32_de vs oracle WL" % name, cfg, mean_g, se_g, np.array(r["mean_lng"]),
-               np.array(r["std_lng"]) / np.sqrt(r["runs"]))
+           np.array(t["se"]), loose=wl_truth_bound(r["mean_lng"], t["lng"]))
+    _check("%s WL fp32_de vs oracle WL" % name, cfg, mean_g, se_g, np.array(r["mean_lng"]),
+           np.array(r["std_lng"]) / np.sqrt(r["runs"]))

@@ -6,7 +6,9 @@ of a small workload (the parity reference), and, for the range that reaches
 down towards the ordered state, ln g from a fixed-weight oracle run (no
 Wang-Landau modification error; a Wang-Landau mean, the oracle's included,
 differs from it by a smooth tilt of a few hundredths at ln f = 2^-18, which
-is reported and bounded by 0.1).  Here the same workload runs as many independent
+is reported and bounded by the oracle's own Wang-Landau mean's distance
+from it plus 0.1; that distance is about 0.26 at the lowest bin of the low
+range).  Here the same workload runs as many independent
 instances in one GPU context (distinct Philox streams), and the mean
 normalised joined ln g is compared with the references:
   * every bin's Delta within 5 combined standard errors (the paper's
@@ -25,7 +27,7 @@ import sys
 import numpy as np
 import pytest
 
-from helpers import gpu_from
+from helpers import gpu_from, wl_truth_bound
 
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
@@ -39,7 +41,7 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _check(tag, cfg, mean_g, se_g, mean_r, se_r, strict=True):
+def _check(tag, cfg, mean_g, se_g, mean_r, se_r, loose=None):
     from oracle.analysis import cv_peak, normalise
     ok = np.isfinite(mean_g) & np.isfinite(mean_r)
     assert ok.sum() >= 0.9 * len(mean_r)
@@ -54,11 +56,12 @@ def _check(tag, cfg, mean_g, se_g, mean_r, se_r, strict=True):
     _say("%s: max|delta| %.4f (bins with se <= 0.004: %d, max|delta| there %.4f) max z %.2f"
          % (tag, np.nanmax(np.abs(delta[ok])), tight.sum(),
             np.abs(delta[tight]).max() if tight.any() else 0.0, z.max()))
-    if not strict:
+    if loose is not None:
         # a Wang-Landau mean against the fixed-weight ln g: the estimator's
-        # own error at this final ln f (the oracle's Wang-Landau mean shows the
-        # same smooth tilt of a few hundredths against it)
-        assert np.nanmax(np.abs(delta[ok])) <= 0.1
+        # own error at this final ln f, bounded by the oracle's Wang-Landau
+        # mean's distance from the same reference plus a margin
+        _say("%s: bound %.3f" % (tag, loose))
+        assert np.nanmax(np.abs(delta[ok])) <= loose
         return np.nanmax(np.abs(delta[ok]))
     assert z.max() <= 5.0
     if tight.any():
@@ -109,4 +112,4 @@ def test_statistical_parity_L4(mode, name):
     if name in TRUTH:
         t = json.load(open(os.path.join(GOLD, TRUTH[name])))
         _check("%s %s vs truth" % (name, mode), cfg, mean_g, se_g, np.array(t["lng"]), np.array(t["se"]),
-               strict=False)
+               loose=wl_truth_bound(ref["mean_lng"], t["lng"]))
