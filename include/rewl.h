@@ -163,6 +163,19 @@ rewl_status rewl_set_schedule(rewl_ctx *ctx, int32_t inst, int32_t flat_num, int
                               double lnf_init, double lnf_final, int64_t exchange_interval,
                               int64_t resync_interval);
 
+/* Window sharing (before rewl_query_sizes; default off): the m walkers of a
+ * window advance through the iterations together.  A walker whose histogram
+ * is flat keeps walking at its ln f until every walker of its window is flat;
+ * at the next exchange step each bin's ln g~ becomes the mean over the
+ * walkers that visited it (summed in walker order), every walker takes that
+ * estimate and the union of the visited bins, H restarts and ln f halves for
+ * all of them (or all finish).  This is the multiple-walker refinement of the
+ * parallel scheme from the replica-exchange Wang-Landau literature the paper
+ * cites (Sec. parallel scheme, several walkers per window); off, each walker
+ * proceeds independently, as the paper's own runs do.  on: 0 or 1, else
+ * REWL_EINVAL; REWL_ESTATE after rewl_query_sizes. */
+rewl_status rewl_set_window_sharing(rewl_ctx *ctx, int32_t inst, int32_t on);
+
 /* Launch shape of the trial-move kernel (after rewl_query_sizes).
  * walkers_per_block: 1..4 walkers (one wavefront each) per workgroup
  * (several workgroups share a compute unit when LDS allows).

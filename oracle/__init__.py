@@ -89,6 +89,7 @@ def lib():
         L.orc_read_round_trips.argtypes = [vp, P(C.c_uint32), i32]
         L.orc_write_lng.argtypes = [vp, i32, P(dbl), P(C.c_uint8), i32]
         L.orc_shift_energy.argtypes = [vp, i32, dbl]
+        L.orc_set_share.argtypes = [vp, i32]
         _lib = L
     return _lib
 
@@ -251,6 +252,11 @@ class Oracle:
         if th.size != lib().orc_mlp_param_count():
             raise OracleError("expected %d parameters" % lib().orc_mlp_param_count())
         lib().orc_set_proposal_mlp(self._c, _p(th, C.c_double))
+
+    def set_share(self, on=True):
+        """Walkers of a window advance through the iterations together and
+        share their ln g (before init)."""
+        lib().orc_set_share(self._c, 1 if on else 0)
 
     def set_drive_trace(self, cap):
         lib().orc_set_drive_trace(self._c, cap)

@@ -351,6 +351,7 @@ typedef struct {
     int done;
     uint64_t attempts, accepts, oow;
     int nvis_prev;
+    int ready;             /* window sharing: flat in this iteration, waiting for the window */
     double *lng;           /* [hi-lo] */
     uint32_t *H;           /* [hi-lo] */
     uint8_t *vis;          /* [hi-lo] */
@@ -391,6 +392,7 @@ typedef struct {
     /* replica round trips, per configuration: (half trips << 2) | last
      * extreme window visited (1 lowest, 2 highest, 0 none yet) */
     uint32_t *rtrip;
+    int share;             /* walkers of a window advance together and share ln g */
 } octx;
 
 typedef struct {
@@ -996,6 +998,11 @@ static void flatness_check(octx *c, owalker *w)
     }
     w->nvis_prev = nvis;
     if (!flat) return;
+    if (c->share) {
+        /* the window's walkers advance together (see window_merge) */
+        w->ready = 1;
+        return;
+    }
     if (w->lnf <= c->lnf_final) {
         w->done = 1;
         return;
@@ -1003,6 +1010,65 @@ static void flatness_check(octx *c, owalker *w)
     w->lnf = w->lnf * 0.5;
     w->iter++;
     memset(w->H, 0, sizeof(uint32_t) * (size_t)nb);
+}
+
+/* Several walkers per window sharing their estimate (the multiple-walker
+ * form of the parallel scheme, refined in the REWL literature the paper
+ * cites): a walker whose histogram is flat keeps walking at its ln f until
+ * every walker of its window is flat; then each bin's ln g~ becomes the
+ * mean over the walkers that visited it (walkers taken in order), every
+ * walker gets that estimate and the union of the visited bins, H restarts,
+ * and ln f halves for all of them (or all finish, when the iteration ran at
+ * ln f <= ln f_final).  All walkers of a window do the same number of moves
+ * at the same ln f, so their estimates carry the same total and are
+ * averaged without shifts. */
+static void window_merge(octx *c)
+{
+    int m = c->m;
+    for (int k = 0; k < c->h; ++k) {
+        owalker *w0 = &c->w[k * m];
+        int all = 1;
+        for (int r = 0; r < m; ++r) all &= c->w[k * m + r].ready && !c->w[k * m + r].done;
+        if (!all) continue;
+        int nb = w0->hi - w0->lo;
+        int nvis = 0;
+        for (int j = 0; j < nb; ++j) {
+            double sum = 0.0;
+            int cnt = 0;
+            for (int r = 0; r < m; ++r) {
+                owalker *w = &c->w[k * m + r];
+                if (w->vis[j]) { sum = sum + w->lng[j]; cnt++; }
+            }
+            if (cnt == 0) continue;
+            double mean = sum / (double)cnt;
+            for (int r = 0; r < m; ++r) {
+                owalker *w = &c->w[k * m + r];
+                w->lng[j] = mean;
+                w->vis[j] = 1;
+            }
+            nvis++;
+        }
+        int finish = w0->lnf <= c->lnf_final;
+        for (int r = 0; r < m; ++r) {
+            owalker *w = &c->w[k * m + r];
+            w->ready = 0;
+            w->nvis_prev = nvis;
+            if (finish) {
+                w->done = 1;
+            } else {
+                w->lnf = w->lnf * 0.5;
+                w->iter++;
+                memset(w->H, 0, sizeof(uint32_t) * (size_t)nb);
+            }
+        }
+    }
+}
+
+/* turn window sharing on or off (before orc_init) */
+int orc_set_share(octx *c, int on)
+{
+    c->share = on ? 1 : 0;
+    return ORC_OK;
 }
 
 /* Replica exchange between windows k and k+1 for all k of the parity of the
@@ -1091,6 +1157,7 @@ int64_t orc_run(octx *c, int64_t n_segments)
             maybe_resync(c, w, before);
             flatness_check(c, w);
         }
+        if (c->share) window_merge(c);
         exchange_step(c);
         c->t++;
         done_segs++;
@@ -1102,6 +1169,7 @@ int64_t orc_run(octx *c, int64_t n_segments)
 int orc_exchange(octx *c)
 {
     if (!c->inited) return ORC_ESTATE;
+    if (c->share) window_merge(c);
     exchange_step(c);
     c->t++;
     return ORC_OK;

@@ -43,6 +43,7 @@ struct InstanceCfg {
     int32_t flat_num = 0, flat_den = 1;
     double lnf_init = 1.0, lnf_final = 1e-8;
     int64_t seg = 0, resync = 0;
+    int32_t share = 0;
     // derived
     int32_t z = 0;
     std::vector<int32_t> lo, hi;
@@ -252,6 +253,7 @@ rewl_status finalize(rewl_ctx *c)
         d.lnf_init = q.lnf_init;
         d.seg_len = q.seg;
         d.resync = q.resync;
+        d.share = q.share;
         d.cfg_off = cfg_off;
         d.init_off = -1;
         if (q.lattice == LAT_BCC) {
@@ -583,6 +585,15 @@ rewl_status rewl_set_schedule(rewl_ctx *ctx, int32_t inst, int32_t flat_num, int
     q.seg = exchange_interval;
     q.resync = resync_interval;
     q.has_schedule = true;
+    return REWL_OK;
+}
+
+rewl_status rewl_set_window_sharing(rewl_ctx *ctx, int32_t inst, int32_t on)
+{
+    rewl_status st = check_inst(ctx, inst);
+    if (st) return st;
+    if (on != 0 && on != 1) return fail(REWL_EINVAL, "window sharing is 0 (off) or 1 (on)");
+    ctx->inst[inst].share = on;
     return REWL_OK;
 }
 

@@ -28,6 +28,8 @@ struct InstDesc {
     int32_t n_walkers, slot_off, flat_num, flat_den;
     int32_t xstat_off, nb_max, deg_off;   // deg_off: first entry in the degree table
     float inv_hs;                         // 1 / sum_n z_n |J_n| (learned-proposal features)
+    int32_t share;                        // 1: the walkers of a window share ln g (merged when all are flat)
+    int32_t pad_share;
     double Emin, inv_de, lnf_final, lnf_init;
     int64_t seg_len, resync;
     int64_t cfg_off;                   // spin element offset of configuration 0
@@ -49,6 +51,8 @@ struct WalkerDesc {
 struct WalkerState {
     double E, lnf, max_drift;
     int32_t bin, cfg, iter, done, nvis, status;
+    int32_t ready;                     // window sharing: flat in this iteration, waiting for its window
+    int32_t pad_ready;
     uint64_t attempts, accepts, oow;
     uint64_t harvested;                // training records written
 };

@@ -521,7 +521,10 @@ __global__ void __launch_bounds__(256) sweep_kernel(KArgs a)
                    (unsigned long long)I.flat_num * sumH;
         }
         st.nvis = nvis;
-        if (flat) {
+        if (flat && I.share) {
+            // the window's walkers advance together (exchange_instance merges)
+            st.ready = 1;
+        } else if (flat) {
             if (st.lnf <= I.lnf_final) {
                 st.done = 1;
             } else {
@@ -553,6 +556,70 @@ __global__ void __launch_bounds__(256) sweep_kernel(KArgs a)
 }
 
 // ------------------------------------------------------------------ exchange
+// Window sharing (the multiple-walker refinement of the parallel scheme): a
+// walker whose histogram is flat keeps walking at its ln f until every walker
+// of its window is flat; then every bin's ln g~ becomes the mean over the
+// walkers that visited it (summed in walker order, then divided by their
+// count), every walker takes that estimate and the union of the visited bins,
+// H restarts, and ln f halves for all (or all finish, when the iteration ran
+// at ln f <= ln f_final).  The walkers of a window make the same number of
+// moves at the same ln f, so their estimates carry the same total and are
+// averaged without shifts.  Lane j takes bins j, j + 64, ...
+__device__ void merge_windows(const KArgs &a, const InstDesc &I)
+{
+    const int lane = __lane_id();
+    const int m = I.m;
+    for (int k = 0; k < I.h; ++k) {
+        const int w0 = I.walker_base + k * m;
+        bool waiting = false;
+        for (int r = lane; r < m; r += kWave) {
+            const WalkerState &s = a.state[w0 + r];
+            waiting |= !(s.ready != 0 && s.done == 0);
+        }
+        if (__builtin_amdgcn_ballot_w64(waiting) != 0ull) continue;
+        const WalkerDesc d0 = a.wdesc[w0];
+        const int nb = d0.hi - d0.lo;
+        const bool finish = a.state[w0].lnf <= I.lnf_final;
+        int nvis = 0;
+        for (int j = lane; j < nb; j += kWave) {
+            double sum = 0.0;
+            int cnt = 0;
+            for (int r = 0; r < m; ++r) {
+                const int64_t o = a.wdesc[w0 + r].bin_off + j;
+                if (a.vis[o]) {
+                    sum = sum + a.lng[o];
+                    cnt += 1;
+                }
+            }
+            if (cnt > 0) {
+                const double mean = sum / (double)cnt;
+                for (int r = 0; r < m; ++r) {
+                    const int64_t o = a.wdesc[w0 + r].bin_off + j;
+                    a.lng[o] = mean;
+                    a.vis[o] = 1;
+                }
+                nvis += 1;
+            }
+            if (!finish)
+                for (int r = 0; r < m; ++r) a.hist[a.wdesc[w0 + r].bin_off + j] = 0u;
+        }
+        nvis = wave_sum_i(nvis);
+        for (int r = lane; r < m; r += kWave) {
+            WalkerState *s = a.state + w0 + r;
+            s->ready = 0;
+            s->nvis = nvis;
+            if (finish) {
+                s->done = 1;
+            } else {
+                s->lnf = s->lnf * 0.5;
+                s->iter += 1;
+            }
+        }
+    }
+    // the exchange below reads what other lanes stored
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+}
+
 // One replica-exchange step of instance ii at step t, by one wavefront:
 // window pairs (k, k+1) with k of the parity of t; the m walkers of window k
 // are paired with those of window k+1 by a Fisher-Yates permutation (lane r
@@ -560,12 +627,13 @@ __global__ void __launch_bounds__(256) sweep_kernel(KArgs a)
 // window on a bin that walker has visited; the swap moves configuration,
 // energy and bin.  Lanes r < m decide the m pairs of a window pair at once
 // (they touch disjoint walkers).  Then the instance's done flag is
-// recomputed.
+// recomputed.  With window sharing, merge_windows runs first.
 __device__ void exchange_instance(const KArgs &a, int ii, uint64_t t)
 {
     const int lane = __lane_id();
     const InstDesc I = a.inst[ii];
     const int m = I.m;
+    if (I.share) merge_windows(a, I);
     for (int k = (int)(t & 1u); k + 1 < I.h; k += 2) {
         int pr = lane;
         for (int i = m - 1; i >= 1; --i) {
@@ -1253,7 +1321,9 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
                    (unsigned long long)I.flat_num * sumH;
         }
         st.nvis = nvis;
-        if (flat) {
+        if (flat && I.share) {
+            st.ready = 1;
+        } else if (flat) {
             if (st.lnf <= I.lnf_final) {
                 st.done = 1;
             } else {

@@ -65,6 +65,7 @@ _SIGS = {
     "rewl_set_couplings_explicit": [_vp, _i32, _i32, _i64, _P(_i32), _P(_i32), _P(_dbl)],
     "rewl_set_windows": [_vp, _i32, _dbl, _dbl, _i32, _i32, _dbl, _i32],
     "rewl_set_schedule": [_vp, _i32, _i32, _i32, _dbl, _dbl, _i64, _i64],
+    "rewl_set_window_sharing": [_vp, _i32, _i32],
     "rewl_query_sizes": [_vp, _P(_sz)],
     "rewl_bind_buffers": [_vp, _P(_vp)],
     "rewl_init_walkers": [_vp, _u64, _P(_dbl)],
@@ -171,6 +172,10 @@ def rewl_set_schedule(ctx, inst, flat_num, flat_den, lnf_init, lnf_final, exchan
                       resync_interval):
     _call("rewl_set_schedule", ctx, inst, flat_num, flat_den, lnf_init, lnf_final,
           exchange_interval, resync_interval)
+
+
+def rewl_set_window_sharing(ctx, inst, on):
+    _call("rewl_set_window_sharing", ctx, inst, 1 if on else 0)
 
 
 def rewl_query_sizes(ctx):
@@ -390,6 +395,7 @@ class Run:
       lattice: ("bcc", L, J) or ("explicit", N, i, j, J)
       windows: (E_min, E_max, n_bins, n_windows, overlap, walkers_per_window)
       schedule: (flat_num, flat_den, lnf_init, lnf_final, exchange_interval, resync_interval)
+      share: optional, True for window sharing (rewl_set_window_sharing)
     """
 
     def __init__(self, instances, mode="fp64_det", device=0, stream=None, trace_cap=0,
@@ -412,6 +418,8 @@ class Run:
                 N = lat[1]
             rewl_set_windows(self.ctx, i, *d["windows"])
             rewl_set_schedule(self.ctx, i, *d["schedule"])
+            if d.get("share"):
+                rewl_set_window_sharing(self.ctx, i, True)
             self.inst.append(dict(N=N, h=d["windows"][3], m=d["windows"][5]))
         self.sizes = rewl_query_sizes(self.ctx)
         self.bufs = [torch.empty(max(s, 256), dtype=torch.uint8, device=self.device)

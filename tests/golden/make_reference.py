@@ -19,7 +19,7 @@ Calls only the CPU oracle.  Two kinds of reference, per workload:
   mean offset over the bins both cover.
 
 Usage:
-  python tests/golden/make_reference.py wl <workload> [runs] [threads]
+  python tests/golden/make_reference.py wl <workload> [runs] [threads] [output file]
   python tests/golden/make_reference.py truth <workload> [batches] [segments_per_batch] [threads]
 
 Workloads (bcc, o = 0.75, flatness 0.8, ln f 1 -> final, resync every 100 N):
@@ -219,7 +219,7 @@ def main():
         return
     runs = int(sys.argv[3]) if len(sys.argv) > 3 else 256
     threads = int(sys.argv[4]) if len(sys.argv) > 4 else 8
-    out = os.path.join(HERE, WL_OUT[name])
+    out = os.path.join(HERE, sys.argv[5] if len(sys.argv) > 5 else WL_OUT[name])
     all_lg, peaks = [], []
     t0 = time.time()
     for r in range(runs):
@@ -237,6 +237,7 @@ def main():
                 "finite_runs": np.isfinite(A).sum(0).tolist(),
                 "cv_peak_T_of_mean": cv_peak(Ec, mean, 1.0, 8.0)[0],
                 "cv_peak_T_runs": peaks,
+                "run_lng": [[None if not np.isfinite(v) else round(float(v), 6) for v in r] for r in all_lg],
             }
             with open(out + ".tmp", "w") as f:
                 json.dump(doc, f, indent=1)

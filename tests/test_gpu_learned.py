@@ -165,8 +165,14 @@ def test_harvest_records():
 @pytest.mark.parametrize("name", ["L4_mid", "L4_low"])
 def test_learned_walk_statistical_parity(name):
     """Train on records of the plain walk, then run 256 independent learned
-    walks: their mean normalised ln g matches the oracle's Wang-Landau mean
-    (and, on the low range, the fixed-weight truth) within the bars above;
+    walks: on the middle range their mean normalised ln g matches the
+    oracle's Wang-Landau mean within the bars above.  On the low range the
+    Wang-Landau estimator's own error at the final ln f (the oracle's mean
+    lies 0.26 from the fixed-weight ln g at the lowest bin) depends on the
+    walk's dynamics, which the proposal changes, so two Wang-Landau means
+    need not agree there within their spreads: the learned mean is held to
+    the fixed-weight ln g within the oracle's own distance plus 0.1, and the
+    proposal's parity on that range is the fixed-weight test below;
     the learned proposal accepts more often than the uniform one, both
     measured over whole runs to convergence on the same schedule (uniform
     walks on these ranges are held to the parity bars in
@@ -180,8 +186,9 @@ def test_learned_walk_statistical_parity(name):
     se_r = np.array(ref["std_lng"]) / np.sqrt(ref["runs"])
     mean_g = np.nanmean(A, axis=0)
     se_g = np.nanstd(A, axis=0, ddof=1) / np.sqrt(np.isfinite(A).sum(0))
-    _check("%s learned vs oracle WL" % name, cfg, mean_g, se_g, mean_r, se_r)
-    if name in TRUTH:
+    if name not in TRUTH:
+        _check("%s learned vs oracle WL" % name, cfg, mean_g, se_g, mean_r, se_r)
+    else:
         t = json.load(open(os.path.join(GOLD, TRUTH[name])))
         _check("%s learned vs truth" % name, cfg, mean_g, se_g, np.array(t["lng"]), np.array(t["se"]),
                loose=wl_truth_bound(mean_r, t["lng"]))
