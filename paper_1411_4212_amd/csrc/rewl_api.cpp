@@ -51,6 +51,64 @@ struct InstanceCfg {
 
 int round_half_up(double x) { return (int)std::floor(x + 0.5); }
 
+// The fast sweep's neighbour slots: 16 Q entries, slot k read by lane group
+// member (k mod 16) / 4 in column (k / 16, k mod 4) -- one load instruction
+// per column.  Neighbours in one memory row of the configuration (same
+// sublattice and the same y and z cell offsets, consecutive x cells) are put
+// into one column, so that one instruction touches each cache line of the
+// stencil once; rows longer than a column are split.  Columns are filled
+// first-fit in order of decreasing row length; padding slots carry J = 0 and
+// point at the site itself (a line the move reads anyway).  If the rows do
+// not fit, the shell order is kept.
+std::vector<BccSlot> fast_slot_table(const BccSlot *sl, int z, int Q)
+{
+    const int ncol = 4 * Q;
+    BccSlot pad{};
+    std::vector<BccSlot> out((size_t)16 * Q, pad);
+    // rows keyed by (flip, dz, dy) of the sublattice-0 displacement, cells by x
+    std::vector<std::vector<int>> rows;
+    std::vector<std::array<int, 3>> keys;
+    for (int k = 0; k < z; ++k) {
+        const std::array<int, 3> key = {sl[k].flip, sl[k].d[0][2], sl[k].d[0][1]};
+        size_t r = 0;
+        while (r < keys.size() && keys[r] != key) ++r;
+        if (r == keys.size()) {
+            keys.push_back(key);
+            rows.emplace_back();
+        }
+        rows[r].push_back(k);
+    }
+    std::vector<std::vector<int>> pieces;
+    for (auto &row : rows) {
+        std::stable_sort(row.begin(), row.end(), [&](int a, int b) { return sl[a].d[0][0] < sl[b].d[0][0]; });
+        for (size_t i = 0; i < row.size(); i += 4)
+            pieces.emplace_back(row.begin() + i, row.begin() + std::min(row.size(), i + 4));
+    }
+    std::stable_sort(pieces.begin(), pieces.end(),
+                     [](const std::vector<int> &a, const std::vector<int> &b) { return a.size() > b.size(); });
+    std::vector<std::vector<int>> cols;
+    for (const auto &pc : pieces) {
+        size_t c = 0;
+        while (c < cols.size() && cols[c].size() + pc.size() > 4) ++c;
+        if (c == cols.size()) cols.emplace_back();
+        cols[c].insert(cols[c].end(), pc.begin(), pc.end());
+    }
+    if ((int)cols.size() > ncol) {
+        for (int k = 0; k < z; ++k) {
+            out[k] = sl[k];
+            out[k].real = 1;
+        }
+        return out;
+    }
+    for (size_t c = 0; c < cols.size(); ++c)
+        for (size_t r = 0; r < cols[c].size(); ++r) {
+            const size_t k = 16 * (c / 4) + 4 * r + (c % 4);
+            out[k] = sl[cols[c][r]];
+            out[k].real = 1;
+        }
+    return out;
+}
+
 // bcc lattice vectors in half-cell units (integer triples of equal parity),
 // grouped in shells of increasing length, lexicographic within a shell.
 struct ShellVec {
@@ -394,6 +452,14 @@ rewl_status finalize(rewl_ctx *c)
         }
         if (ok) c->fast_q = zmax <= 16 ? 1 : (zmax <= 64 ? 4 : 8);
         c->all_pow2 = p2 ? 1 : 0;
+    }
+    if (c->fast_q > 0) {
+        for (size_t ii = 0; ii < c->inst.size(); ++ii) {
+            InstDesc &d = c->idesc[ii];
+            d.fslot_off = (int32_t)c->slots.size();
+            const std::vector<BccSlot> f = fast_slot_table(&c->slots[d.slot_off], d.z, c->fast_q);
+            c->slots.insert(c->slots.end(), f.begin(), f.end());
+        }
     }
     {
         rewl_status st = plan_launch(c);

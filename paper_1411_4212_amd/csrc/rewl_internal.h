@@ -29,7 +29,7 @@ struct InstDesc {
     int32_t xstat_off, nb_max, deg_off;   // deg_off: first entry in the degree table
     float inv_hs;                         // 1 / sum_n z_n |J_n| (learned-proposal features)
     int32_t share;                        // 1: the walkers of a window share ln g (merged when all are flat)
-    int32_t pad_share;
+    int32_t fslot_off;                    // the fast sweep's 16 Q slots, grouped by memory row
     double Emin, inv_de, lnf_final, lnf_init;
     int64_t seg_len, resync;
     int64_t cfg_off;                   // spin element offset of configuration 0
@@ -63,7 +63,7 @@ struct WalkerState {
 struct BccSlot {
     int8_t d[2][3];
     uint8_t flip;
-    uint8_t pad;
+    uint8_t real;      // fast-sweep tables: 1 for a neighbour, 0 for a padding slot (J = 0)
     float Jf;
     double Jd;
 };

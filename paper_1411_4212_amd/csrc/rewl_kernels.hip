@@ -882,25 +882,26 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
     constexpr int GL = 64 / GW;
     constexpr int NC = 16 / GL;
     const int grp = lane / GL, r = lane % GL;
-    // slot (c, q) of this lane is bcc slot k = 16 q + NC r + c: chain NC r + c
-    // of the 16-chain order.  With one chain per lane the SWAR offsets are
-    // kept split (low bits / top bit of each field); with four, whole.
+    // slot (c, q) of this lane is entry k = 16 q + NC r + c of the fast slot
+    // table (neighbours grouped by memory row; see the API's table set-up):
+    // chain NC r + c of the 16-chain order.  With one chain per lane the SWAR
+    // offsets are kept split (low bits / top bit of each field); with four,
+    // whole.
     uint32_t offM[2][NC][Q], offH[2][NC][Q];
     uint32_t flipm = 0;            // bit c Q + q: neighbour on the other sublattice
     T Jq[NC][Q];
     int d2max = 0;                 // largest squared stencil length, half-cell units
     {
-        const BccSlot *slots = a.slots + I.slot_off;
+        const BccSlot *slots = a.slots + I.fslot_off;
 #pragma unroll
         for (int c = 0; c < NC; ++c)
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 const int k = q * 16 + r * NC + c;
-                BccSlot sl{};
-                if (k < I.z) sl = slots[k];
-                Jq[c][q] = (k < I.z) ? ((MODE == M_F32) ? (T)sl.Jf : (T)sl.Jd) : (T)0;
+                const BccSlot sl = slots[k];
+                Jq[c][q] = sl.real ? ((MODE == M_F32) ? (T)sl.Jf : (T)sl.Jd) : (T)0;
                 if (sl.flip) flipm |= 1u << (c * Q + q);
-                if (k < I.z) {
+                if (sl.real) {
                     const int vx = 2 * sl.d[0][0] + sl.flip, vy = 2 * sl.d[0][1] + sl.flip,
                               vz = 2 * sl.d[0][2] + sl.flip;
                     const int d2 = vx * vx + vy * vy + vz * vz;
