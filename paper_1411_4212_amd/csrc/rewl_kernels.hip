@@ -88,6 +88,10 @@ struct LatCtx {
     const int32_t *nbr;
     const double *J;
     const BccSlot *slots;   // full slot table (DET sequential walk)
+    // storage order of the configuration these functions read: -1 for one
+    // staged in LDS (site order), the instance's layout for one in HBM
+    int lay, lgk;
+    __device__ __forceinline__ int at(int i) const { return spin_slot(i, lay, lgk); }
 };
 
 template <int MODE>
@@ -98,6 +102,8 @@ __device__ __forceinline__ void load_latctx(LatCtx<MODE> &c, const InstDesc &I, 
     c.z = I.z;
     c.invL = I.L > 0 ? 1.0f / (float)I.L : 0.0f;
     c.lattice = I.lattice;
+    c.lay = -1;
+    c.lgk = I.lg_L;
     c.slots = a.slots + I.slot_off;
     c.deg = a.tdeg ? a.tdeg + I.deg_off : nullptr;
     c.nbr = a.tnbr ? a.tnbr + I.tab_off : nullptr;
@@ -129,7 +135,7 @@ __device__ __forceinline__ void local_field(const LatCtx<MODE> &c, const typenam
             for (int k = 0; k < c.z; ++k) {
                 const BccSlot sl = c.slots[k];
                 const int j = bcc_neighbour(site, c.L, c.invL, sl);
-                const V s = S[j];
+                const V s = S[c.at(j)];
                 ax = ax + sl.Jd * s.x;
                 ay = ay + sl.Jd * s.y;
                 az = az + sl.Jd * s.z;
@@ -139,7 +145,7 @@ __device__ __forceinline__ void local_field(const LatCtx<MODE> &c, const typenam
             for (int k = 0; k < d; ++k) {
                 const int j = c.nbr[(int64_t)site * c.z + k];
                 const double Jv = c.J[(int64_t)site * c.z + k];
-                const V s = S[j];
+                const V s = S[c.at(j)];
                 ax = ax + Jv * s.x;
                 ay = ay + Jv * s.y;
                 az = az + Jv * s.z;
@@ -154,7 +160,7 @@ __device__ __forceinline__ void local_field(const LatCtx<MODE> &c, const typenam
         if (c.lattice == LAT_BCC) {
             if (c.has0) {
                 const int j = bcc_neighbour(site, c.L, c.invL, c.s0);
-                const V s = S[j];
+                const V s = S[c.at(j)];
                 const T Jv = (MODE == M_F32) ? (T)c.s0.Jf : (T)c.s0.Jd;
                 px = Jv * s.x;
                 py = Jv * s.y;
@@ -162,7 +168,7 @@ __device__ __forceinline__ void local_field(const LatCtx<MODE> &c, const typenam
             }
             if (c.has1) {
                 const int j = bcc_neighbour(site, c.L, c.invL, c.s1);
-                const V s = S[j];
+                const V s = S[c.at(j)];
                 const T Jv = (MODE == M_F32) ? (T)c.s1.Jf : (T)c.s1.Jd;
                 px += Jv * s.x;
                 py += Jv * s.y;
@@ -173,7 +179,7 @@ __device__ __forceinline__ void local_field(const LatCtx<MODE> &c, const typenam
             for (int k = lane; k < d; k += kWave) {
                 const int j = c.nbr[(int64_t)site * c.z + k];
                 const T Jv = (T)c.J[(int64_t)site * c.z + k];
-                const V s = S[j];
+                const V s = S[c.at(j)];
                 px += Jv * s.x;
                 py += Jv * s.y;
                 pz += Jv * s.z;
@@ -204,7 +210,7 @@ __device__ double full_energy(const LatCtx<MODE> &c, const typename Spin<MODE>::
         for (int i = 0; i < c.N; ++i) {
             double hx, hy, hz;
             local_field<MODE>(c, S, i, hx, hy, hz);
-            const V s = S[i];
+            const V s = S[c.at(i)];
             acc = acc + ((s.x * hx + s.y * hy) + s.z * hz);
         }
         return -0.5 * acc;
@@ -217,7 +223,7 @@ __device__ double full_energy(const LatCtx<MODE> &c, const typename Spin<MODE>::
                 for (int k = 0; k < c.z; ++k) {
                     const BccSlot sl = c.slots[k];
                     const int j = bcc_neighbour(i, c.L, c.invL, sl);
-                    const V s = S[j];
+                    const V s = S[c.at(j)];
                     hx += sl.Jd * (double)s.x;
                     hy += sl.Jd * (double)s.y;
                     hz += sl.Jd * (double)s.z;
@@ -227,13 +233,13 @@ __device__ double full_energy(const LatCtx<MODE> &c, const typename Spin<MODE>::
                 for (int k = 0; k < d; ++k) {
                     const int j = c.nbr[(int64_t)i * c.z + k];
                     const double Jv = c.J[(int64_t)i * c.z + k];
-                    const V s = S[j];
+                    const V s = S[c.at(j)];
                     hx += Jv * (double)s.x;
                     hy += Jv * (double)s.y;
                     hz += Jv * (double)s.z;
                 }
             }
-            const V s = S[i];
+            const V s = S[c.at(i)];
             acc += ((double)s.x * hx + (double)s.y * hy) + (double)s.z * hz;
         }
         return -0.5 * wave_sum_d(acc);
@@ -268,12 +274,19 @@ __device__ __forceinline__ double delta_e(typename Spin<MODE>::T nx, typename Sp
     }
 }
 
-// Copy a walker's configuration between HBM and LDS (all lanes).
+// Copy a walker's configuration from HBM (instance layout) into LDS (site
+// order), and back (all lanes).
 template <int MODE>
-__device__ __forceinline__ void copy_spins(typename Spin<MODE>::V *dst, const typename Spin<MODE>::V *src,
-                                           int N)
+__device__ __forceinline__ void spins_to_lds(typename Spin<MODE>::V *S, const typename Spin<MODE>::V *G,
+                                             const InstDesc &I)
 {
-    for (int i = __lane_id(); i < N; i += kWave) dst[i] = src[i];
+    for (int i = __lane_id(); i < I.N; i += kWave) S[i] = G[spin_slot(i, I.layout, I.lg_L)];
+}
+template <int MODE>
+__device__ __forceinline__ void spins_to_hbm(typename Spin<MODE>::V *G, const typename Spin<MODE>::V *S,
+                                             const InstDesc &I)
+{
+    for (int i = __lane_id(); i < I.N; i += kWave) G[spin_slot(i, I.layout, I.lg_L)] = S[i];
 }
 
 // ------------------------------------------------------------------ init
@@ -296,6 +309,7 @@ __global__ void __launch_bounds__(256) init_kernel(KArgs a)
     V *S = LDS_SPINS ? (V *)L.spins : G;
     LatCtx<MODE> c;
     load_latctx<MODE>(c, I, a, lane);
+    if (!LDS_SPINS) c.lay = I.layout;
 
     for (int i = lane; i < I.N; i += kWave) {
         double x, y, z;
@@ -312,7 +326,7 @@ __global__ void __launch_bounds__(256) init_kernel(KArgs a)
         v.y = (T)y;
         v.z = (T)z;
         v.w = (T)0;
-        S[i] = v;
+        S[c.at(i)] = v;
     }
     wave_sync();
 
@@ -332,7 +346,7 @@ __global__ void __launch_bounds__(256) init_kernel(KArgs a)
         propose<MODE>(a.seed, wd.stream, n, TAG_INIT_SPHERE, nx, ny, nz);
         T hx, hy, hz;
         local_field<MODE>(c, S, i, hx, hy, hz);
-        const V si = S[i];
+        const V si = S[c.at(i)];
         const double Eb = E + delta_e<MODE>(nx, ny, nz, si, hx, hy, hz);
         const double xb = (Eb - I.Emin) * I.inv_de;
         const bool in_b = (xb >= lo && xb < hi);
@@ -342,13 +356,13 @@ __global__ void __launch_bounds__(256) init_kernel(KArgs a)
             v.y = ny;
             v.z = nz;
             v.w = (T)0;
-            S[i] = v;
+            S[c.at(i)] = v;
             E = Eb;
             inside = in_b;
         }
     }
     wave_sync();
-    if (LDS_SPINS) copy_spins<MODE>(G, S, I.N);
+    if (LDS_SPINS) spins_to_hbm<MODE>(G, S, I);
     if (lane == 0) {
         WalkerState st{};
         st.E = E;
@@ -390,7 +404,7 @@ __global__ void __launch_bounds__(256) sweep_kernel(KArgs a)
 
     const int nb = wd.hi - wd.lo;
     V *G = (V *)a.spins + I.cfg_off + (int64_t)st.cfg * I.N;
-    copy_spins<MODE>(S, G, I.N);
+    spins_to_lds<MODE>(S, G, I);
     double *glng = a.lng + wd.bin_off;
     uint32_t *gH = a.hist + wd.bin_off;
     uint8_t *gvis = a.vis + wd.bin_off;
@@ -538,7 +552,7 @@ __global__ void __launch_bounds__(256) sweep_kernel(KArgs a)
     }
     wave_sync();
 
-    copy_spins<MODE>(G, S, I.N);
+    spins_to_hbm<MODE>(G, S, I);
     for (int j = lane; j < nb; j += kWave) {
         glng[j] = L.lng[j];
         gH[j] = L.H[j];
@@ -851,7 +865,7 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
     // spins in LDS for the segment, or read and written in place in HBM
     V *G = (V *)a.spins + I.cfg_off + (int64_t)st.cfg * N;
     V *S = LDS_SPINS ? (V *)Ld.spins : G;
-    if (LDS_SPINS) copy_spins<MODE>(S, G, N);
+    if (LDS_SPINS) spins_to_lds<MODE>(S, G, I);
     double *glng = a.lng + wd.bin_off;
     uint32_t *gH = a.hist + wd.bin_off;
     uint8_t *gvis = a.vis + wd.bin_off;
@@ -968,6 +982,8 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
     const bool harvesting = a.harvest != nullptr && !LEARNED;
     uint64_t hcount = st.harvested;
     const int twoL = 2 * fl.L;
+    // storage order of the configuration in HBM (LDS holds site order)
+    const int lay = I.layout, lgk = I.lg_L;
     // half-cell coordinates (2x + s, 2y + s, 2z + s) of a move's site from its code
     auto halfcell = [&](int code, int &hx_, int &hy_, int &hz_) {
         int x, y, zc, sb;
@@ -992,12 +1008,13 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
         const int code = b_code[e];
         const int site = b_site[e];
         // the site's own spin and the proposal are read with the gather
-        const V si = S[site];
+        const V si = S[LDS_SPINS ? site : spin_slot(site, lay, lgk)];
         const V pr = b_prop[e];
         mv_site = site;
         mv_prop = pr;
         if constexpr (NC > 1) halfcell(code, mhx, mhy, mhz);
         T px[NC], py[NC], pz[NC];
+        T gx[NC][Q], gy[NC][Q], gz[NC][Q];
 #pragma unroll
         for (int c = 0; c < NC; ++c) px[c] = py[c] = pz[c] = (T)0;
         const int sb = (POW2 || fl.pow2) ? (code >> (3 * fl.k)) : (code >> 24);
@@ -1025,11 +1042,23 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
                     sum -= gt * (uint32_t)fl.L;
                     j = (int)(sum & 0xFF) + fl.L * ((int)((sum >> 8) & 0xFF) + fl.L * ((int)(sum >> 16) + fl.L * t));
                 }
+                if constexpr (!LDS_SPINS) j = spin_slot(j, lay, lgk);
                 if constexpr (NC == 1) nidx[q] = j;
                 const V s = S[j];
-                px[c] = fma_t<T>(Jq[c][q], s.x, px[c]);
-                py[c] = fma_t<T>(Jq[c][q], s.y, py[c]);
-                pz[c] = fma_t<T>(Jq[c][q], s.z, pz[c]);
+                gx[c][q] = s.x;
+                gy[c][q] = s.y;
+                gz[c][q] = s.z;
+            }
+        // all of this lane's neighbour loads are issued above, before the
+        // first sum below waits for one: the pass pays one memory latency,
+        // not one per slot
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                px[c] = fma_t<T>(Jq[c][q], gx[c][q], px[c]);
+                py[c] = fma_t<T>(Jq[c][q], gy[c][q], py[c]);
+                pz[c] = fma_t<T>(Jq[c][q], gz[c][q], pz[c]);
             }
         T hx, hy, hz;
         if constexpr (NC == 1) {
@@ -1227,10 +1256,10 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
                             v.y = (T)psy;
                             v.z = (T)psz;
                             v.w = (T)0;
-                            S[site] = v;
+                            S[LDS_SPINS ? site : spin_slot(site, lay, lgk)] = v;
                         }
                     } else {
-                        if (lane == GL * g) S[site] = mv_prop;
+                        if (lane == GL * g) S[LDS_SPINS ? site : spin_slot(site, lay, lgk)] = mv_prop;
                     }
                     // one lane stored the spin; other lanes of this wavefront
                     // gather it for later moves
@@ -1243,8 +1272,9 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
                     bool hit;
                     if constexpr (NC == 1) {
                         hit = (grp > g) && (mv_site == site);
+                        const int sslot = LDS_SPINS ? site : spin_slot(site, lay, lgk);
 #pragma unroll
-                        for (int q = 0; q < Q; ++q) hit |= (grp > g) && (nidx[q] == site);
+                        for (int q = 0; q < Q; ++q) hit |= (grp > g) && (nidx[q] == sslot);
                     } else {
                         int ax, ay, az;
                         halfcell(__builtin_amdgcn_readlane(b_code_reg, p + g), ax, ay, az);
@@ -1289,6 +1319,7 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
     // resync when due (lane-parallel FP64 energy)
     LatCtx<MODE> c;
     load_latctx<MODE>(c, I, a, lane);
+    if (!LDS_SPINS) c.lay = lay;
     if (I.resync > 0 && (n / (uint64_t)I.resync) != (n_begin / (uint64_t)I.resync)) {
         const double ef = full_energy<MODE>(c, S);
         const double d = fabs(ef - E);
@@ -1341,7 +1372,7 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
     }
     wave_sync();
 
-    if (LDS_SPINS) copy_spins<MODE>(G, S, N);
+    if (LDS_SPINS) spins_to_hbm<MODE>(G, S, I);
     for (int j = lane; j < nb; j += kWave) {
         const double v = Ld.lng[j];
         const bool vis = !__builtin_isnan(v);
