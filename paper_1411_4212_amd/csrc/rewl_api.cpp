@@ -51,14 +51,7 @@ struct InstanceCfg {
 
 int round_half_up(double x) { return (int)std::floor(x + 0.5); }
 
-// Brick edge 2^kBrickBits cells for configurations of bcc lattices with L a
-// power of two (spin_slot).  0 (sublattices interleaved per cell) measured
-// fastest on the L=32 eight-shell workload, ahead of bricks of 2, 4 and 8
-// cells by 1-4 % and of the site order by 7 %.
-#ifndef REWL_BRICK_BITS
-#define REWL_BRICK_BITS 0
-#endif
-constexpr int kBrickBits = REWL_BRICK_BITS;
+
 
 // The fast sweep's neighbour slots: 16 Q entries, slot k read by lane group
 // member (k mod 16) / 4 in column (k / 16, k mod 4) -- one load instruction
@@ -324,8 +317,11 @@ rewl_status finalize(rewl_ctx *c)
         d.layout = -1;
         d.lg_L = 0;
         if (q.lattice == LAT_BCC && (q.L & (q.L - 1)) == 0) {
+            // sublattices interleaved per cell: on the L=32 eight-shell
+            // workload 7 % faster than the site order, and 1-4 % ahead of
+            // bricks of 2, 4 and 8 cells per edge (measured, not kept)
             while ((1 << d.lg_L) < q.L) ++d.lg_L;
-            d.layout = std::min(kBrickBits, d.lg_L);
+            d.layout = 0;
         }
         d.cfg_off = cfg_off;
         d.init_off = -1;

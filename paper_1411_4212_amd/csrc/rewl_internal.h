@@ -30,7 +30,7 @@ struct InstDesc {
     float inv_hs;                         // 1 / sum_n z_n |J_n| (learned-proposal features)
     int32_t share;                        // 1: the walkers of a window share ln g (merged when all are flat)
     int32_t fslot_off;                    // the fast sweep's 16 Q slots, grouped by memory row
-    int32_t layout;                       // storage order of a configuration in HBM (spin_slot)
+    int32_t layout;                       // storage order of a configuration in HBM (spin_slot): -1 or 0
     int32_t lg_L;                         // log2 L when L is a power of two, else 0
     double Emin, inv_de, lnf_final, lnf_init;
     int64_t seg_len, resync;
@@ -133,20 +133,15 @@ struct KArgs {
 };
 
 // Storage slot of site i (site order ((s L + z) L + y) L + x) in a
-// configuration held in HBM.  layout < 0: the site order itself.  layout =
-// b >= 0 (bcc, L = 2^k, b <= k): from the low bits up, the sublattice s, then
-// x, y and z inside a brick of 2^b cells per edge, then the brick's x, y and
-// z.  b = 0 keeps cells in site order with the two sublattice sites of a cell
-// side by side, so that the two sublattices' rows of a move's stencil share
-// cache lines; b > 0 also groups neighbouring y and z rows.
+// configuration held in HBM.  layout < 0: the site order itself.  layout = 0
+// (bcc, L = 2^k): cells in site order with the two sublattice sites of a cell
+// side by side, slot = 2 (i mod L^3) + s, so that the two sublattices' rows
+// of a move's stencil share cache lines.
 __host__ __device__ inline int spin_slot(int i, int layout, int k)
 {
     if (layout < 0) return i;
-    const uint32_t u = (uint32_t)i, m = (1u << k) - 1u, b = (uint32_t)layout, bm = (1u << b) - 1u;
-    const uint32_t x = u & m, y = (u >> k) & m, z = (u >> (2 * k)) & m, s = u >> (3 * k);
-    const uint32_t hk = (uint32_t)k - b;
-    return (int)(s | ((x & bm) << 1) | ((y & bm) << (1 + b)) | ((z & bm) << (1 + 2 * b)) |
-                 ((x >> b) << (1 + 3 * b)) | ((y >> b) << (1 + 3 * b + hk)) | ((z >> b) << (1 + 3 * b + 2 * hk)));
+    const uint32_t u = (uint32_t)i, c = u & ((1u << (3 * k)) - 1u);
+    return (int)((c << 1) | (u >> (3 * k)));
 }
 
 constexpr int kWave = 64;

@@ -1035,14 +1035,17 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
                         om = o & fl.M;
                         oh = o & fl.Hm;
                     }
-                    j = (int)((((aa & fl.M) + om) ^ (aa & fl.Hm) ^ oh) | ((uint32_t)t << (3 * fl.k)));
+                    const uint32_t cell = ((aa & fl.M) + om) ^ (aa & fl.Hm) ^ oh;
+                    // site order in LDS; in HBM the storage order (spin_slot)
+                    j = (LDS_SPINS || lay < 0) ? (int)(cell | ((uint32_t)t << (3 * fl.k)))
+                                               : (int)((cell << 1) | (uint32_t)t);
                 } else {
                     uint32_t sum = ((uint32_t)code & 0x00FFFFFFu) + (sb ? offM[1][c][q] : offM[0][c][q]);
                     const uint32_t gt = ((sum + wrapC) >> 7) & 0x00010101u;
                     sum -= gt * (uint32_t)fl.L;
+                    // L not a power of two: HBM holds site order (layout -1)
                     j = (int)(sum & 0xFF) + fl.L * ((int)((sum >> 8) & 0xFF) + fl.L * ((int)(sum >> 16) + fl.L * t));
                 }
-                if constexpr (!LDS_SPINS) j = spin_slot(j, lay, lgk);
                 if constexpr (NC == 1) nidx[q] = j;
                 const V s = S[j];
                 gx[c][q] = s.x;
@@ -1051,7 +1054,10 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
             }
         // all of this lane's neighbour loads are issued above, before the
         // first sum below waits for one: the pass pays one memory latency,
-        // not one per slot
+        // not one per slot.  The scheduling barrier keeps the compiler from
+        // moving each sum up to its load (which it does under register
+        // pressure, leaving a full memory wait after every load).
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int c = 0; c < NC; ++c)
 #pragma unroll
