@@ -210,8 +210,9 @@ def extra_measurements(torch, workloads, Run):
     """The same kernels on other workloads, each with an autotuned launch
     shape: the 64 uneven instances in the persistent kernel, the L=16
     eight-shell workload (1024 walkers) with the uniform and with the learned
-    proposal (trained on its own plain walk), and the shape of the paper's
-    largest run (L=40, 893 windows x 1 walker, two shells)."""
+    proposal (trained on its own plain walk), the shape of the paper's
+    largest run (L=40, 893 windows x 1 walker, two shells), and the walk over
+    the magnetisation M_z on bcc L=8."""
     out = {}
     cfgs = workloads.batched(64)
     r = Run([dict(lattice=c["lattice"], windows=c["windows"], schedule=c["schedule"]) for c in cfgs],
@@ -248,6 +249,20 @@ def extra_measurements(torch, workloads, Run):
                 walkers_per_block=lc["walkers_per_block"], spins_in_lds=lc["spins_in_lds"], **info)
             r.close()
             log("bench: %s %s %.3e attempts/s (%s)" % (name, kind, rate, "LDS" if lc["spins_in_lds"] else "HBM"))
+    # the walk over the magnetisation M_z (generic sweep kernel): bcc L=8,
+    # M_z in [-64, 64) on 64 bins (about +-3.5 standard deviations of the
+    # infinite-temperature distribution), 8 windows x 8 walkers
+    wl = dict(lattice=("bcc", 8, list(workloads.J_C2)), windows=(-64.0, 64.0, 64, 8, 0.75, 8),
+              schedule=(4, 5, 1.0, 2.0 ** -20, 10000, 102400), coord="Mz")
+    r = Run([wl], mode="fp32_de")
+    r.init(11)
+    lc = r.launch()
+    rate, dt = _timed(r, lambda: r.run(4), torch)
+    out["Mz_L8_uniform"] = dict(walkers=r.n_walkers, attempts_per_s=rate, seconds=dt, segments=4,
+                                coordinate="M_z", kernel="sweep_kernel (fp32_de, generic)",
+                                walkers_per_block=lc["walkers_per_block"], spins_in_lds=lc["spins_in_lds"])
+    r.close()
+    log("bench: Mz_L8 %.3e attempts/s" % rate)
     return out
 
 

@@ -176,6 +176,16 @@ rewl_status rewl_set_schedule(rewl_ctx *ctx, int32_t inst, int32_t flat_num, int
  * REWL_EINVAL; REWL_ESTATE after rewl_query_sizes. */
 rewl_status rewl_set_window_sharing(rewl_ctx *ctx, int32_t inst, int32_t on);
 
+/* The walk's coordinate (before rewl_query_sizes; default 0): 0 = the energy
+ * of Eq. 1; 1 = the magnetisation along z, M_z = sum_i S_i^z (Sec. original
+ * WL: the density of states may be taken over another order parameter).
+ * With 1, rewl_set_windows' E_min, E_max and bins are over M_z, every E in the
+ * walker state and trace holds M_z, and the walk runs in the generic sweep
+ * kernel (a context with such an instance has no fast sweep, persistent
+ * form or learned proposal: those calls return REWL_EUNSUPPORTED).
+ * coord outside {0, 1}: REWL_EINVAL; after rewl_query_sizes: REWL_ESTATE. */
+rewl_status rewl_set_coordinate(rewl_ctx *ctx, int32_t inst, int32_t coord);
+
 /* Launch shape of the trial-move kernel (after rewl_query_sizes).
  * walkers_per_block: 1..4 walkers (one wavefront each) per workgroup
  * (several workgroups share a compute unit when LDS allows).

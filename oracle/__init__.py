@@ -90,6 +90,7 @@ def lib():
         L.orc_write_lng.argtypes = [vp, i32, P(dbl), P(C.c_uint8), i32]
         L.orc_shift_energy.argtypes = [vp, i32, dbl]
         L.orc_set_share.argtypes = [vp, i32]
+        L.orc_set_coordinate.argtypes = [vp, i32]
         _lib = L
     return _lib
 
@@ -252,6 +253,13 @@ class Oracle:
         if th.size != lib().orc_mlp_param_count():
             raise OracleError("expected %d parameters" % lib().orc_mlp_param_count())
         lib().orc_set_proposal_mlp(self._c, _p(th, C.c_double))
+
+    def set_coordinate(self, coord):
+        """The walk's coordinate: "E" (energy, default) or "Mz" (magnetisation
+        along z); before init.  Windows and bins are then over that value."""
+        code = {"E": 0, "Mz": 1}[coord]
+        if lib().orc_set_coordinate(self._c, code) != 0:
+            raise OracleError("bad coordinate")
 
     def set_share(self, on=True):
         """Walkers of a window advance through the iterations together and

@@ -19,6 +19,10 @@
  *     min(1, g_i(E_A) g_j(E_B) / (g_i(E_B) g_j(E_A))), possible only
  *     if both replicas lie in the overlap                          (Sec. parallel scheme; Sec. simulation details)
  *   - trial move: random site, new direction uniform on the sphere (Sec. simulation details)
+ *   - optional: the walk over another coordinate, the magnetisation M_z
+ *     instead of E                                                 (Sec. original WL)
+ *   - optional: the walkers of a window sharing ln g~ (the multiple-walker
+ *     refinement of the parallel scheme)                           (Sec. parallel scheme)
  *
  * Readings where the paper is silent (documented with the design):
  *   flatness is taken over the bins the walker has visited; a check in a
@@ -393,7 +397,26 @@ typedef struct {
      * extreme window visited (1 lowest, 2 highest, 0 none yet) */
     uint32_t *rtrip;
     int share;             /* walkers of a window advance together and share ln g */
+    int coord;             /* the walk's coordinate: 0 energy, 1 magnetisation M_z */
 } octx;
+
+/* The coordinate the walk bins (Sec. original WL: the density of states may
+ * be taken over another order parameter instead of E): the energy of Eq. 1,
+ * or the magnetisation along z, M_z = sum_i S_i^z, summed in site order.   */
+static double full_coord(const octx *c, const double *S)
+{
+    if (!c->coord) return full_energy(&c->lat, S);
+    double m = 0.0;
+    for (int i = 0; i < c->lat.N; ++i) m = m + S[3 * (size_t)i + 2];
+    return m;
+}
+
+/* change of the coordinate when S_i becomes Sn (h: the local field at i) */
+static double coord_delta(const octx *c, const double *Sold, const double *Sn, const double h[3])
+{
+    if (c->coord) return Sn[2] - Sold[2];
+    return delta_e(Sold, Sn, h);
+}
 
 typedef struct {
     uint32_t site;
@@ -753,7 +776,7 @@ static int drive_into_window(octx *c, owalker *w)
         double sn[3], h[3];
         orc_sphere(c->seed, w->stream, n, TAG_INIT_SPHERE, sn);
         local_field(&c->lat, S, i, h);
-        double Eb = w->E + delta_e(S + 3 * (size_t)i, sn, h);
+        double Eb = w->E + coord_delta(c, S + 3 * (size_t)i, sn, h);
         int inside = in_window(c, Eb, w->lo, w->hi, &b);
         int acc = inside || window_distance(c, Eb, w->lo, w->hi) < window_distance(c, w->E, w->lo, w->hi);
         if (c->drive && n < (uint64_t)c->drive_cap) {
@@ -848,7 +871,7 @@ int orc_init(octx *c, uint32_t seed, const double *init_spins)
                 orc_sphere(seed, w->stream, (uint64_t)i, TAG_INIT_CONFIG, S + 3 * (size_t)i);
             }
         }
-        w->E = full_energy(&c->lat, S);
+        w->E = full_coord(c, S);
     }
     #pragma omp parallel for schedule(static) num_threads(c->n_threads > 0 ? c->n_threads : omp_get_max_threads())
     for (int wi = 0; wi < c->W; ++wi) {
@@ -898,7 +921,7 @@ static void wl_attempt(octx *c, owalker *w)
         mix_sample(&m, u_mix, u_w, u_phi, uni, sn);
         lnq_ratio = mix_log_q(&m, si) - mix_log_q(&m, sn);
     }
-    double Eb = w->E + delta_e(si, sn, h);
+    double Eb = w->E + coord_delta(c, si, sn, h);
     int bb;
     int acc = 0, outside = 0, newbin = 0;
     double lnb = 0.0;
@@ -931,7 +954,7 @@ static void wl_attempt(octx *c, owalker *w)
         w->bin = bb;
         w->accepts++;
         if (c->check_energy) {
-            double ef = full_energy(&c->lat, S);
+            double ef = full_coord(c, S);
             double err = fabs(ef - w->E);
             if (err > c->max_check_err) c->max_check_err = err;
         }
@@ -961,7 +984,7 @@ static void maybe_resync(octx *c, owalker *w, uint64_t before)
     if (c->resync <= 0) return;
     uint64_t R = (uint64_t)c->resync;
     if (w->attempts / R == before / R) return;
-    double ef = full_energy(&c->lat, cfg_spins(c, w->cfg));
+    double ef = full_coord(c, cfg_spins(c, w->cfg));
     double d = fabs(ef - w->E);
     if (d > w->max_drift) w->max_drift = d;
     w->E = ef;
@@ -1062,6 +1085,15 @@ static void window_merge(octx *c)
             }
         }
     }
+}
+
+/* the walk's coordinate: 0 energy (default), 1 magnetisation M_z (before
+ * orc_init; windows and bins are then over M_z) */
+int orc_set_coordinate(octx *c, int coord)
+{
+    if (coord != 0 && coord != 1) return ORC_EINVAL;
+    c->coord = coord;
+    return ORC_OK;
 }
 
 /* turn window sharing on or off (before orc_init) */

@@ -44,6 +44,7 @@ struct InstanceCfg {
     double lnf_init = 1.0, lnf_final = 1e-8;
     int64_t seg = 0, resync = 0;
     int32_t share = 0;
+    int32_t coord = 0;
     // derived
     int32_t z = 0;
     std::vector<int32_t> lo, hi;
@@ -314,6 +315,7 @@ rewl_status finalize(rewl_ctx *c)
         d.seg_len = q.seg;
         d.resync = q.resync;
         d.share = q.share;
+        d.coord = q.coord;
         d.layout = -1;
         d.lg_L = 0;
         if (q.lattice == LAT_BCC && (q.L & (q.L - 1)) == 0) {
@@ -457,7 +459,8 @@ rewl_status finalize(rewl_ctx *c)
         for (size_t ii = 0; ii < c->inst.size(); ++ii) {
             const InstanceCfg &q = c->inst[ii];
             const bool pow2 = (q.L & (q.L - 1)) == 0;
-            ok &= q.lattice == LAT_BCC && q.L >= 4 && (pow2 || q.L <= 64);
+            // the fast sweep walks in energy only
+            ok &= q.lattice == LAT_BCC && q.L >= 4 && (pow2 || q.L <= 64) && q.coord == 0;
             p2 &= pow2;
             zmax = std::max(zmax, c->idesc[ii].z);
         }
@@ -671,6 +674,15 @@ rewl_status rewl_set_window_sharing(rewl_ctx *ctx, int32_t inst, int32_t on)
     if (st) return st;
     if (on != 0 && on != 1) return fail(REWL_EINVAL, "window sharing is 0 (off) or 1 (on)");
     ctx->inst[inst].share = on;
+    return REWL_OK;
+}
+
+rewl_status rewl_set_coordinate(rewl_ctx *ctx, int32_t inst, int32_t coord)
+{
+    rewl_status st = check_inst(ctx, inst);
+    if (st) return st;
+    if (coord != 0 && coord != 1) return fail(REWL_EINVAL, "coordinate is 0 (energy) or 1 (magnetisation M_z)");
+    ctx->inst[inst].coord = coord;
     return REWL_OK;
 }
 

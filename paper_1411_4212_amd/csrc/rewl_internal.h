@@ -32,6 +32,8 @@ struct InstDesc {
     int32_t fslot_off;                    // the fast sweep's 16 Q slots, grouped by memory row
     int32_t layout;                       // storage order of a configuration in HBM (spin_slot): -1 or 0
     int32_t lg_L;                         // log2 L when L is a power of two, else 0
+    int32_t coord;                        // the walk's coordinate: 0 energy, 1 magnetisation M_z
+    int32_t pad_coord;
     double Emin, inv_de, lnf_final, lnf_init;
     int64_t seg_len, resync;
     int64_t cfg_off;                   // spin element offset of configuration 0

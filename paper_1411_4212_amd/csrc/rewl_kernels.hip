@@ -92,6 +92,7 @@ struct LatCtx {
     // staged in LDS (site order), the instance's layout for one in HBM
     int lay, lgk;
     __device__ __forceinline__ int at(int i) const { return spin_slot(i, lay, lgk); }
+    int coord;              // the walk's coordinate: 0 energy, 1 M_z
 };
 
 template <int MODE>
@@ -104,6 +105,7 @@ __device__ __forceinline__ void load_latctx(LatCtx<MODE> &c, const InstDesc &I, 
     c.lattice = I.lattice;
     c.lay = -1;
     c.lgk = I.lg_L;
+    c.coord = I.coord;
     c.slots = a.slots + I.slot_off;
     c.deg = a.tdeg ? a.tdeg + I.deg_off : nullptr;
     c.nbr = a.tnbr ? a.tnbr + I.tab_off : nullptr;
@@ -246,6 +248,24 @@ __device__ double full_energy(const LatCtx<MODE> &c, const typename Spin<MODE>::
     }
 }
 
+// The walk's coordinate over a whole configuration: the energy, or
+// M_z = sum_i S_i^z (DET: FP64 in site order; other modes: lane partial sums
+// in FP64, then the wavefront sum).
+template <int MODE>
+__device__ double full_value(const LatCtx<MODE> &c, const typename Spin<MODE>::V *S)
+{
+    if (!c.coord) return full_energy<MODE>(c, S);
+    if constexpr (MODE == M_DET) {
+        double m = 0.0;
+        for (int i = 0; i < c.N; ++i) m = m + (double)S[c.at(i)].z;
+        return m;
+    } else {
+        double m = 0.0;
+        for (int i = __lane_id(); i < c.N; i += kWave) m += (double)S[c.at(i)].z;
+        return wave_sum_d(m);
+    }
+}
+
 // Proposal direction in the spin type of the mode.
 template <int MODE>
 __device__ __forceinline__ void propose(uint32_t seed, uint32_t stream, uint64_t n, uint32_t tag,
@@ -272,6 +292,20 @@ __device__ __forceinline__ double delta_e(typename Spin<MODE>::T nx, typename Sp
     } else {
         return -(((nx - s.x) * hx + (ny - s.y) * hy) + (nz - s.z) * hz);
     }
+}
+
+// Change of the walk's coordinate when S_i becomes S' = (nx, ny, nz): dE
+// from the local field, or nz - S_i^z for M_z.
+template <int MODE>
+__device__ __forceinline__ double move_delta(const LatCtx<MODE> &c, const typename Spin<MODE>::V *S, int i,
+                                             typename Spin<MODE>::T nx, typename Spin<MODE>::T ny,
+                                             typename Spin<MODE>::T nz, const typename Spin<MODE>::V &si)
+{
+    using T = typename Spin<MODE>::T;
+    if (c.coord) return (double)(nz - si.z);
+    T hx, hy, hz;
+    local_field<MODE>(c, S, i, hx, hy, hz);
+    return delta_e<MODE>(nx, ny, nz, si, hx, hy, hz);
 }
 
 // Copy a walker's configuration from HBM (instance layout) into LDS (site
@@ -330,7 +364,7 @@ __global__ void __launch_bounds__(256) init_kernel(KArgs a)
     }
     wave_sync();
 
-    double E = full_energy<MODE>(c, S);
+    double E = full_value<MODE>(c, S);
     const double lo = (double)wd.lo, hi = (double)wd.hi;
     auto dist = [&](double e) {
         const double x = (e - I.Emin) * I.inv_de;
@@ -344,10 +378,8 @@ __global__ void __launch_bounds__(256) init_kernel(KArgs a)
         const int i = pick_site(r.x, I.N);
         T nx, ny, nz;
         propose<MODE>(a.seed, wd.stream, n, TAG_INIT_SPHERE, nx, ny, nz);
-        T hx, hy, hz;
-        local_field<MODE>(c, S, i, hx, hy, hz);
         const V si = S[c.at(i)];
-        const double Eb = E + delta_e<MODE>(nx, ny, nz, si, hx, hy, hz);
+        const double Eb = E + move_delta<MODE>(c, S, i, nx, ny, nz, si);
         const double xb = (Eb - I.Emin) * I.inv_de;
         const bool in_b = (xb >= lo && xb < hi);
         if (in_b || dist(Eb) < dist(E)) {
@@ -435,10 +467,8 @@ __global__ void __launch_bounds__(256) sweep_kernel(KArgs a)
         const double u = u53(r.y, r.z);
         T nx, ny, nz;
         propose<MODE>(a.seed, wd.stream, n, TAG_SPHERE, nx, ny, nz);
-        T hx, hy, hz;
-        local_field<MODE>(c, S, i, hx, hy, hz);
         const V si = S[i];
-        const double Eb = E + delta_e<MODE>(nx, ny, nz, si, hx, hy, hz);
+        const double Eb = E + move_delta<MODE>(c, S, i, nx, ny, nz, si);
         const double xb = (Eb - Emin) * inv;
         int bb = -1;
         bool outside = true;
@@ -504,7 +534,7 @@ __global__ void __launch_bounds__(256) sweep_kernel(KArgs a)
     // resync: recompute E from scratch when the attempt count crossed a
     // multiple of the resync interval during this segment
     if (I.resync > 0 && (n / (uint64_t)I.resync) != (st.attempts / (uint64_t)I.resync)) {
-        const double ef = full_energy<MODE>(c, S);
+        const double ef = full_value<MODE>(c, S);
         const double d = fabs(ef - E);
         if (d > st.max_drift) st.max_drift = d;
         E = ef;
@@ -1327,7 +1357,7 @@ __device__ __forceinline__ void fast_segment(const KArgs &a, const int w, const 
     load_latctx<MODE>(c, I, a, lane);
     if (!LDS_SPINS) c.lay = lay;
     if (I.resync > 0 && (n / (uint64_t)I.resync) != (n_begin / (uint64_t)I.resync)) {
-        const double ef = full_energy<MODE>(c, S);
+        const double ef = full_value<MODE>(c, S);
         const double d = fabs(ef - E);
         if (d > st.max_drift) st.max_drift = d;
         E = ef;

@@ -66,6 +66,7 @@ _SIGS = {
     "rewl_set_windows": [_vp, _i32, _dbl, _dbl, _i32, _i32, _dbl, _i32],
     "rewl_set_schedule": [_vp, _i32, _i32, _i32, _dbl, _dbl, _i64, _i64],
     "rewl_set_window_sharing": [_vp, _i32, _i32],
+    "rewl_set_coordinate": [_vp, _i32, _i32],
     "rewl_query_sizes": [_vp, _P(_sz)],
     "rewl_bind_buffers": [_vp, _P(_vp)],
     "rewl_init_walkers": [_vp, _u64, _P(_dbl)],
@@ -176,6 +177,10 @@ def rewl_set_schedule(ctx, inst, flat_num, flat_den, lnf_init, lnf_final, exchan
 
 def rewl_set_window_sharing(ctx, inst, on):
     _call("rewl_set_window_sharing", ctx, inst, 1 if on else 0)
+
+
+def rewl_set_coordinate(ctx, inst, coord):
+    _call("rewl_set_coordinate", ctx, inst, {"E": 0, "Mz": 1}[coord] if isinstance(coord, str) else coord)
 
 
 def rewl_query_sizes(ctx):
@@ -396,6 +401,7 @@ class Run:
       windows: (E_min, E_max, n_bins, n_windows, overlap, walkers_per_window)
       schedule: (flat_num, flat_den, lnf_init, lnf_final, exchange_interval, resync_interval)
       share: optional, True for window sharing (rewl_set_window_sharing)
+      coord: optional, "E" (default) or "Mz" (rewl_set_coordinate)
     """
 
     def __init__(self, instances, mode="fp64_det", device=0, stream=None, trace_cap=0,
@@ -420,6 +426,8 @@ class Run:
             rewl_set_schedule(self.ctx, i, *d["schedule"])
             if d.get("share"):
                 rewl_set_window_sharing(self.ctx, i, True)
+            if d.get("coord", "E") != "E":
+                rewl_set_coordinate(self.ctx, i, d["coord"])
             self.inst.append(dict(N=N, h=d["windows"][3], m=d["windows"][5]))
         self.sizes = rewl_query_sizes(self.ctx)
         self.bufs = [torch.empty(max(s, 256), dtype=torch.uint8, device=self.device)

@@ -19,6 +19,8 @@ def oracle_from(cfg, threads=4, trace=0, check_energy=False):
         o.set_check_energy(True)
     if cfg.get("share"):
         o.set_share(True)
+    if cfg.get("coord", "E") != "E":
+        o.set_coordinate(cfg["coord"])
     o.init(cfg["seed"])
     return o
 
@@ -30,7 +32,7 @@ def gpu_from(cfgs, mode, trace=0, seed=None, walkers_per_block=1, residency=0):
     if isinstance(cfgs, dict):
         cfgs = [cfgs]
     r = Run([dict(lattice=c["lattice"], windows=c["windows"], schedule=c["schedule"],
-                  share=c.get("share", False)) for c in cfgs], mode=mode, trace_cap=trace, walkers_per_block=walkers_per_block,
+                  share=c.get("share", False), coord=c.get("coord", "E")) for c in cfgs], mode=mode, trace_cap=trace, walkers_per_block=walkers_per_block,
             residency=residency)
     starts = [init_spins(c) for c in cfgs]
     if all(s is None for s in starts):
