@@ -43,6 +43,8 @@ MLP_FLOP_PER_ATTEMPT = 2 * (4 * 64 + 64 * 64 + 64 * 12)    # one 4-64-64-12 eval
 MEASURED_TRAFFIC = {
     # profiles/sweep_fast_c2_fp32_counters.md: FETCH 1355.0 KiB x 2.00 + WRITE 2754.5 KiB x 1.00
     ("60a24928d224d1fc", "c2", "lds"): 5595648,
+    # profiles/persistent_c5_fp32_learned_counters.md: FETCH 24,162,000 KiB x 2.00 + WRITE 650,540 KiB x 1.00
+    ("d6d81c611cdab2a8", "c5", "hbm"): 50149928960,
 }
 # Instruction mix of the same launches (SQ counters, one rocprofv3 --pmc pass,
 # per trial move): the second axis next to the bandwidth fraction, since a
@@ -53,6 +55,14 @@ MEASURED_ISSUE = {
                                         "salu_insts_per_attempt": 25.7,
                                         "lds_insts_per_attempt": 5.1,
                                         "wave_clk_per_attempt": 845},
+    # profiles/persistent_c5_fp32_learned_counters.md
+    ("d6d81c611cdab2a8", "c5", "hbm"): {"valu_insts_per_attempt": 202.7,
+                                        "salu_insts_per_attempt": 35.3,
+                                        "vmem_insts_per_attempt": 3.57,
+                                        "lds_insts_per_attempt": 2.6,
+                                        "wave_clk_per_attempt": 2534,
+                                        "wait_fraction": 0.46,
+                                        "l2_misses_per_attempt": 38.7},
 }
 KERNEL_SOURCES = ["rewl_kernels.hip", "rewl_device.h", "rewl_internal.h", "rewl_mlp_device.h"]
 SHELL_COUNTS = [8, 6, 12, 24, 8, 6, 24, 24]
