@@ -13,7 +13,7 @@ make_reference.py from the CPU oracle only):
   Wang-Landau mean (the oracle's as well) differs from it by a smooth tilt
   of a few hundredths, the estimator's own error at ln f = 2^-18; that
   difference is reported and bounded by the oracle's own Wang-Landau
-  mean's distance from it plus 0.1 (that distance is about 0.26 at the
+  mean's distance from it plus 0.1 (that distance is about 0.18 at the
   lowest bin of the low range, a few hundredths elsewhere).
 
 Workloads: bcc L=4, J = (1, 0.5), 2 windows x 8 walkers, on the middle of
@@ -168,7 +168,7 @@ def test_learned_walk_statistical_parity(name):
     walks: on the middle range their mean normalised ln g matches the
     oracle's Wang-Landau mean within the bars above.  On the low range the
     Wang-Landau estimator's own error at the final ln f (the oracle's mean
-    lies 0.26 from the fixed-weight ln g at the lowest bin) depends on the
+    lies 0.18 from the fixed-weight ln g at the lowest bin) depends on the
     walk's dynamics, which the proposal changes, so two Wang-Landau means
     need not agree there within their spreads: the learned mean is held to
     the fixed-weight ln g within the oracle's own distance plus 0.1, and the

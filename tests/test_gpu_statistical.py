@@ -7,7 +7,7 @@ down towards the ordered state, ln g from a fixed-weight oracle run (no
 Wang-Landau modification error; a Wang-Landau mean, the oracle's included,
 differs from it by a smooth tilt of a few hundredths at ln f = 2^-18, which
 is reported and bounded by the oracle's own Wang-Landau mean's distance
-from it plus 0.1; that distance is about 0.26 at the lowest bin of the low
+from it plus 0.1; that distance is about 0.18 at the lowest bin of the low
 range).  Here the same workload runs as many independent
 instances in one GPU context (distinct Philox streams), and the mean
 normalised joined ln g is compared with the references:
