@@ -68,3 +68,49 @@ def test_time_to_final_lnf_learned_vs_uniform(name):
     _say("north star %s: median time learned/uniform %.3f, last %.3f; median error %.4f vs %.4f"
          % (name, l["median_done_s"] / u["median_done_s"], l["last_done_s"] / u["last_done_s"],
             l["median_run_err"], u["median_run_err"]))
+
+
+def _errors(L, ref):
+    from oracle.analysis import normalise
+    errs = []
+    for lg in L:
+        ok = np.isfinite(lg) & np.isfinite(ref)
+        d = normalise(lg, ok) - normalise(ref, ok)
+        errs.append(np.nanmax(np.abs(d)))
+    return np.array(errs)
+
+
+@pytest.mark.long_measurement
+@pytest.mark.parametrize("name", ["z50_L6", "z112_L6"])
+def test_uniform_time_to_the_learned_error(name):
+    """The equal-error reading of the benchmark metric: the learned runs to
+    ln f = 2^-20 against uniform runs to 2^-20, 2^-22 and 2^-24 (64 runs
+    each, fresh, same seeds), each with its median time to the end and its
+    median per-run error against the oracle's fixed-weight ln g.  Printed:
+    where the learned runs' error falls on the uniform curve, and the uniform
+    time there (the design notes record the figures).  Asserted: every run
+    finishes and the errors are finite."""
+    t = json.load(open(os.path.join(GOLD, "truth_%s.json" % name)))
+    wl = t["workload"]
+    ref = np.array(t["lng"])
+    from paper_1411_4212_amd.converge import race
+    rows = []
+    for prop, k in (("learned", 20), ("uniform", 20), ("uniform", 22), ("uniform", 24)):
+        sch = list(wl["schedule"])
+        sch[3] = 2.0 ** -k
+        cfg = dict(lattice=tuple(wl["lattice"]), windows=tuple(wl["windows"]), schedule=tuple(sch))
+        res, L = race(cfg, prop, R=64, chunk=8, cap_s=400.0, log=_say)
+        assert np.isfinite(res["done_at"]).all(), "%s 2^-%d: not every run finished" % (prop, k)
+        e = _errors(L, ref)
+        assert np.isfinite(e).all()
+        rows.append((prop, k, float(np.median(res["done_at"])), float(np.median(e))))
+        _say("%s %s ln f 2^-%d: median time %.2f s, median error %.4f" % (name, prop, k, rows[-1][2], rows[-1][3]))
+    lt, le = rows[0][2], rows[0][3]
+    uni = rows[1:]
+    reached = [(tt, ee) for _, _, tt, ee in uni if ee <= le]
+    if reached:
+        _say("equal error %s: learned %.4f at %.2f s; uniform first at or below it at %.2f s (ratio %.2f)"
+             % (name, le, lt, reached[0][0], reached[0][0] / lt))
+    else:
+        _say("equal error %s: learned %.4f at %.2f s; uniform stays above it down to 2^-24 (%.4f at %.2f s)"
+             % (name, le, lt, uni[-1][3], uni[-1][2]))
