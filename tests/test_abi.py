@@ -77,5 +77,6 @@ def test_bench_measured_figures_are_documented():
     docs = [open(p).read() for p in glob.glob(os.path.join(ROOT, "profiles", "*.md"))]
     for (digest, workload, res), nbytes in bench.MEASURED_TRAFFIC.items():
         assert res in ("lds", "hbm")
-        mark = ("%.3e" % nbytes).replace("e+0", "e")          # e.g. 5.596e6
+        m, e = ("%.3e" % nbytes).split("e")
+        mark = "%se%d" % (m, int(e))                         # e.g. 5.596e6, 5.015e10
         assert any(digest in d and mark in d for d in docs), (digest, workload, mark)
