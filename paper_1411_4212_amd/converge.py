@@ -116,7 +116,7 @@ def run(cfg, proposal="uniform", cap_s=600.0, rounds=256, harvest_iter=8, harves
 
 
 def race(cfg, proposal="uniform", R=64, chunk=8, cap_s=600.0, harvest_iter=6, harvest_segments=2,
-         harvest_every=4, epochs=4, seed=11, log=None):
+         harvest_every=4, epochs=4, seed=11, log=None, max_records=10_000_000):
     """R independent REWL runs of one workload in one context, run to the
     end by the persistent kernel; the wall-clock time at which each run's
     last walker finished its final ln f iteration (the paper's stopping
@@ -126,7 +126,9 @@ def race(cfg, proposal="uniform", R=64, chunk=8, cap_s=600.0, harvest_iter=6, ha
     the median walker has reached ln f <= 2^-harvest_iter, (x, S_i) of every
     harvest_every-th move is recorded for harvest_segments segments, the
     network is trained on the device, and the runs continue with the learned
-    proposal.  Harvest and training are inside the measured time."""
+    proposal.  Harvest and training are inside the measured time; the
+    harvest takes every k-th move with k at least harvest_every and large
+    enough to keep the records under max_records."""
     import torch
     from . import analysis, learned, workloads
     from .rewl import Run, rewl_set_harvest
@@ -159,7 +161,10 @@ def race(cfg, proposal="uniform", R=64, chunk=8, cap_s=600.0, harvest_iter=6, ha
         if proposal == "learned" and phase == "plain" and np.median(its) >= harvest_iter:
             th = time.perf_counter()
             seg = cfg["schedule"][4]
-            r.set_harvest(harvest_segments * seg // harvest_every + 1, harvest_every)
+            # about 1e7 records at most (what the network needs; long segments
+            # would otherwise make training the larger cost)
+            every = max(harvest_every, -(-harvest_segments * seg * r.n_walkers // max_records))
+            r.set_harvest(harvest_segments * seg // every + 1, every)
             r.run(harvest_segments)
             recs = r.harvested()
             rewl_set_harvest(r.ctx, None, 0, 1)
