@@ -18,7 +18,7 @@ def pytest_configure(config):
 def pytest_collection_modifyitems(config, items):
     if os.environ.get("REWL_LONG_MEASUREMENTS") == "1":
         return
-    skip = pytest.mark.skip(reason="long measurement (about 8 min); set REWL_LONG_MEASUREMENTS=1 to run it")
+    skip = pytest.mark.skip(reason="long measurement (minutes); set REWL_LONG_MEASUREMENTS=1 to run it")
     for item in items:
         if "long_measurement" in item.keywords:
             item.add_marker(skip)
