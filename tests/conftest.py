@@ -30,3 +30,25 @@ def oracle_mod():
     from oracle.build import build_oracle
     build_oracle()
     return oracle
+
+
+@pytest.fixture(autouse=True)
+def _progress_to_terminal(request):
+    """Progress lines of the GPU tests (helpers.progress) go to the terminal
+    with pytest's output capture suspended, so that they appear under -q too."""
+    import helpers
+    capman = request.config.pluginmanager.getplugin("capturemanager")
+
+    def write(msg):
+        if capman is None:
+            print(msg, flush=True)
+            return
+        capman.suspend_global_capture(in_=False)
+        try:
+            print(msg, flush=True)
+        finally:
+            capman.resume_global_capture()
+
+    helpers.set_progress_writer(write)
+    yield
+    helpers.set_progress_writer(None)

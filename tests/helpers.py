@@ -72,3 +72,22 @@ def wl_truth_bound(ref_mean, truth, margin=0.1):
     a, b = np.asarray(ref_mean, dtype=float), np.asarray(truth, dtype=float)
     ok = np.isfinite(a) & np.isfinite(b)
     return float(np.max(np.abs(normalise(a, ok)[ok] - normalise(b, ok)[ok]))) + margin
+
+
+_progress_writer = None
+
+
+def set_progress_writer(fn):
+    global _progress_writer
+    _progress_writer = fn
+
+
+def progress(*a):
+    """A progress line of a long GPU test.  It reaches the terminal even while
+    pytest captures the test's output (tests/conftest.py installs the
+    writer): a run that prints nothing for minutes looks hung."""
+    msg = " ".join(str(x) for x in a)
+    if _progress_writer is not None:
+        _progress_writer(msg)
+    else:
+        print(msg, flush=True)

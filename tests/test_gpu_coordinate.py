@@ -17,7 +17,7 @@ import sys
 import numpy as np
 import pytest
 
-from helpers import gpu_from, oracle_from
+from helpers import gpu_from, oracle_from, progress
 from test_gpu_parity import _compare_state, _compare_trace
 from test_oracle_coordinate import _exact_lng
 
@@ -33,9 +33,7 @@ def _chain(N=4, seed=100):
                 schedule=(4, 5, 1.0, 2.0 ** -12, 20000, 0), seed=seed, coord="Mz")
 
 
-def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
+_say = progress
 
 
 def test_det_mz_walk_bit_exact_bcc():

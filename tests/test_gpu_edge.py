@@ -15,14 +15,12 @@ import sys
 import numpy as np
 import pytest
 
-from helpers import bits, gpu_from
+from helpers import bits, gpu_from, progress
 
 pytestmark = pytest.mark.gpu
 
 
-def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
+_say = progress
 
 
 def _oracle_for(cfg, seed, stream_base, instance, trace=0):

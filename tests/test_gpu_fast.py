@@ -5,14 +5,12 @@ import sys
 import numpy as np
 import pytest
 
-from helpers import gpu_from
+from helpers import gpu_from, progress
 
 pytestmark = pytest.mark.gpu
 
 
-def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
+_say = progress
 
 
 @pytest.mark.parametrize("mode", ["fp32_de", "fp64"])

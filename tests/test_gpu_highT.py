@@ -13,7 +13,7 @@ import sys
 import numpy as np
 import pytest
 
-from helpers import gpu_from
+from helpers import gpu_from, progress
 
 pytestmark = pytest.mark.gpu
 
@@ -56,7 +56,14 @@ def test_edgeworth_dos_near_zero_energy(mode):
     cfg = dict(lattice=("bcc", 8, list(J_C2)), windows=(-300.0, 300.0, 120, 2, 0.75, 4),
                schedule=(4, 5, 1.0, 2.0 ** -14, 20000, 100 * N), seed=13)
     g = gpu_from(cfg, mode)
-    segs = g.run_to_convergence(max_segments=4000, chunk=64)
+    segs = 0
+    while segs < 4000:
+        g.run(64)
+        segs += 64
+        done = g.poll()
+        progress("edgeworth %s: %d segments%s" % (mode, segs, " (all done)" if done else ""))
+        if done:
+            break
     assert g.poll(), "not converged in %d segments" % segs
     bins, lg = run_lng(g, 0)
     E = -300.0 + (bins + 0.5) * 5.0

@@ -32,7 +32,7 @@ import sys
 import numpy as np
 import pytest
 
-from helpers import gpu_from, wl_truth_bound
+from helpers import gpu_from, wl_truth_bound, progress
 
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
@@ -40,9 +40,7 @@ REF = {"L4_mid": "ref_parity_L4.json", "L4_low": "ref_parity_L4_low.json"}
 TRUTH = {"L4_low": "truth_L4_low.json"}
 
 
-def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
+_say = progress
 
 
 def _ref(name):
@@ -214,7 +212,13 @@ def _fixed_weight_lng(cfg, W, params, R, segments):
     # burn-in (the walkers enter their windows from above), then count
     g.run(20)
     H0 = [[g.hist(i, w).astype(np.float64) for w in range(h * m)] for i in range(R)]
-    g.run(segments)
+    done = 0
+    while done < segments:
+        n = min(20, segments - done)
+        g.run(n)
+        g.poll()
+        done += n
+        _say("fixed weight: %d of %d segments" % (done, segments))
     out = []
     for i in range(R):
         acc = np.zeros(B)

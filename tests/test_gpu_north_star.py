@@ -26,14 +26,13 @@ import sys
 
 import numpy as np
 import pytest
+from helpers import progress
 
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
-def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
+_say = progress
 
 
 @pytest.mark.parametrize("name", [pytest.param("L4_low", marks=pytest.mark.long_measurement),

@@ -9,14 +9,12 @@ import sys
 import numpy as np
 import pytest
 
-from helpers import bits, gpu_from, oracle_from
+from helpers import bits, gpu_from, oracle_from, progress
 
 pytestmark = pytest.mark.gpu
 
 
-def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
+_say = progress
 
 
 def _compare_state(o, g, inst=0, walkers=None, check_config=True):

@@ -31,16 +31,14 @@ import sys
 import numpy as np
 import pytest
 
-from helpers import gpu_from, wl_truth_bound
+from helpers import gpu_from, wl_truth_bound, progress
 
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 SHAPES = ["z50_L6", "z112_L6"]
 
 
-def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
+_say = progress
 
 
 def _truth(name):
@@ -124,6 +122,7 @@ def test_fixed_weight_chain_matches_oracle(name, form):
     H0 = [[g.hist(i, w).astype(np.float64) for w in range(h * m)] for i in range(R)]
     for _ in range(segments // 40):
         step(40)
+        g.poll()
         _say("  %s: 40 segments" % form)
     assert g.step() == segments + burn
     est = []

@@ -13,7 +13,7 @@ import sys
 import numpy as np
 import pytest
 
-from helpers import bits, gpu_from, oracle_from
+from helpers import bits, gpu_from, oracle_from, progress
 from test_gpu_parity import _compare_state, _compare_trace
 from test_gpu_persistent import _compare
 
@@ -23,9 +23,7 @@ WL = dict(lattice=("bcc", 4, [1.0, 0.5]), windows=(-400.0, -100.0, 30, 2, 0.75, 
           schedule=(4, 5, 1.0, 2.0 ** -8, 5000, 12800), seed=11, share=True)
 
 
-def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
+_say = progress
 
 
 def _windows_identical(g, inst, h, m):

@@ -27,7 +27,7 @@ import sys
 import numpy as np
 import pytest
 
-from helpers import gpu_from, wl_truth_bound
+from helpers import gpu_from, wl_truth_bound, progress
 
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
@@ -36,9 +36,7 @@ TRUTH = {"L4_low": "truth_L4_low.json"}
 RUNS = 256
 
 
-def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
+_say = progress
 
 
 def _check(tag, cfg, mean_g, se_g, mean_r, se_r, loose=None):

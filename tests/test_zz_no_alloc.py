@@ -6,13 +6,12 @@ import sys
 
 import numpy as np
 import pytest
+from helpers import progress
 
 pytestmark = pytest.mark.gpu
 
 
-def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
+_say = progress
 
 
 def _records(n, seed):
