@@ -92,3 +92,20 @@ def test_mz_context_refuses_fast_only_calls():
         g.run_persistent(1)
     with pytest.raises(RewlError):
         g.set_proposal(learned.init_params(3, torch.device("cuda", 0)))
+
+
+def test_det_mz_walk_with_window_sharing_bit_exact():
+    """The two variants together: an M_z walk whose window walkers share ln g~
+    (bcc L=4, two windows x 2 walkers, to convergence) equals the oracle bit
+    for bit."""
+    cfg = dict(BCC, schedule=(4, 5, 1.0, 2.0 ** -6, 3000, 1280), share=True)
+    o = oracle_from(cfg, trace=3000)
+    n = o.run_to_convergence(max_segments=4000, chunk=1)
+    assert o.all_done()
+    _say("Mz + sharing: oracle done after", n, "segments")
+    g = gpu_from(cfg, "fp64_det", trace=3000)
+    g.run(n)
+    assert g.poll()
+    for w in range(4):
+        _compare_trace(o, g, w, w, 3000)
+    _compare_state(o, g)
