@@ -67,7 +67,7 @@ def test_time_to_final_lnf_learned_vs_uniform(name):
         assert errs.max() <= 1.0
         assert rows[prop]["mean_err"] <= 0.2
     u, l = rows["uniform"], rows["learned"]
-    _say("north star %s: median time learned/uniform %.3f, last %.3f; median error %.4f vs %.4f"
+    _say("time to converge %s: median time learned/uniform %.3f, last %.3f; median error %.4f vs %.4f"
          % (name, l["median_done_s"] / u["median_done_s"], l["last_done_s"] / u["last_done_s"],
             l["median_run_err"], u["median_run_err"]))
 
