@@ -81,6 +81,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def _shape_key(t):
+    """Name of an autotuner trial: walkers per block, residency, grid cap."""
+    k = "%dx%s" % (t["walkers_per_block"], "lds" if t["residency"] == 1 else "hbm")
+    return k + ("/grid%d" % t["max_blocks"] if t.get("max_blocks") else "")
+
+
 def bytes_per_attempt(z, mode="fp32_de"):
     """Algorithmic bytes of one trial move: z neighbour spins and the site's
     own spin (3 components each), ln g read at the proposed bin, and the
@@ -235,8 +241,9 @@ def extra_measurements(torch, workloads, Run):
         "walkers": r.n_walkers, "attempts_per_s": rate, "seconds": dt, "rounds": 3,
         "kernel": "persistent_kernel (fp32_de)", "walkers_per_block": lc["walkers_per_block"],
         "spins_in_lds": lc["spins_in_lds"],
-        "autotune_ms_per_segment": {"%dx%s" % (t["walkers_per_block"], "lds" if t["residency"] == 1 else "hbm"):
-                                    (round(t["ms_per_segment"], 3) if t["status"] == 0 else None) for t in trials}}
+        "grid_cap": r.grid_cap(),
+        "autotune_ms_per_segment": {_shape_key(t): (round(t["ms_per_segment"], 3) if t["status"] == 0 else None)
+                                    for t in trials}}
     r.close()
     log("bench: batched %.3e attempts/s" % rate)
     for name, wl, kinds in (("L16_8shell", workloads.c4(), ("uniform", "learned")),
@@ -326,15 +333,18 @@ def main():
         net = "trained on the device on %d (field, spin) records of the plain walk of this workload " \
               "(%.2f s harvest + training, not timed)" % (nrec, secs)
         log("bench:", net)
+    # warm-up rounds first, so that the autotuner times the walk's steady
+    # regime rather than its first rounds from freshly placed walkers
+    log("bench: warmup", args.warmup)
+    for _ in range(args.warmup):
+        r.run_persistent(1)
     trials = []
     if not args.no_autotune:
-        trials = r.autotune(segments=1, persistent=True)
+        trials = r.autotune(segments=2, persistent=True)
     lc = r.launch()
     W = r.n_walkers
     seg = cfg["schedule"][4]
-    log("bench: warmup", args.warmup, "launch", lc)
-    for _ in range(args.warmup):
-        r.run_persistent(1)
+    log("bench: launch", lc, "grid cap", r.grid_cap())
     torch.cuda.synchronize()
     stream = r.stream
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -343,9 +353,10 @@ def main():
     a0, _ = r.total_attempts()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    grid = 0
     for k in range(args.steps):
         evs[k][0].record(stream)
-        r.run_persistent(1)
+        grid = r.run_persistent(1)
         evs[k][1].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -368,6 +379,7 @@ def main():
         torch.cuda.synchronize()
         log("bench: copy calibration done (3 x 256 MiB)")
     acc = sum(r.walker(0, w)["accepts"] for w in range(W)) / max(1, sum(r.walker(0, w)["attempts"] for w in range(W)))
+    grid_cap = r.grid_cap()
     r.close()
     digest = kernel_digest()
     res = "lds" if lc["spins_in_lds"] else "hbm"
@@ -416,8 +428,8 @@ def main():
                      "avg_launch_ms": avg_launch_s * 1e3, "issue": issue,
                      "mfma_tflops": None if args.uniform else MLP_FLOP_PER_ATTEMPT * per_launch_attempts / avg_launch_s / 1e12,
                      "mfma_frac": None if args.uniform else MLP_FLOP_PER_ATTEMPT * per_launch_attempts / avg_launch_s / 1e12 / BF16_PEAK_TFLOPS,
-                     "autotune_ms_per_round": {"%dx%s" % (t["walkers_per_block"], "lds" if t["residency"] == 1 else "hbm"):
-                                               (round(t["ms_per_segment"], 3) if t["status"] == 0 else None)
+                     "grid": grid, "grid_cap": grid_cap,
+                     "autotune_ms_per_round": {_shape_key(t): (round(t["ms_per_segment"], 3) if t["status"] == 0 else None)
                                                for t in trials}},
         "cpu_baseline": cpu,
         "extra": extra,

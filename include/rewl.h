@@ -196,6 +196,15 @@ rewl_status rewl_set_coordinate(rewl_ctx *ctx, int32_t inst, int32_t coord);
  * previous shape in place. */
 rewl_status rewl_set_launch(rewl_ctx *ctx, int32_t walkers_per_block, int32_t residency);
 
+/* Grid cap of rewl_run_persistent calls that pass max_blocks = 0: at most
+ * max_blocks blocks (0 = every block that can be resident).  Set by the
+ * autotuner's persistent form; rewl_set_launch clears it.  Negative:
+ * REWL_EINVAL. */
+rewl_status rewl_set_grid_cap(rewl_ctx *ctx, int32_t max_blocks);
+
+/* The grid cap in use (rewl_set_grid_cap).  Null argument: REWL_EINVAL. */
+rewl_status rewl_get_grid_cap(rewl_ctx *ctx, int32_t *max_blocks);
+
 /* The launch shape in use: walkers per block, 1 if configurations are staged
  * in LDS, and LDS bytes per workgroup. */
 rewl_status rewl_get_launch(rewl_ctx *ctx, int32_t *walkers_per_block, int32_t *spins_in_lds,
@@ -204,17 +213,22 @@ rewl_status rewl_get_launch(rewl_ctx *ctx, int32_t *walkers_per_block, int32_t *
 /* Launch-shape autotuner.  Times `segments` segments (rewl_run, or one
  * rewl_run_persistent call if persistent != 0) for every walkers-per-block
  * count in {1, 2, 4} and residency in {LDS, HBM} that the context can use,
- * restoring the walk's state before each trial and at the end, so that the
- * walk itself is unchanged; then applies the fastest shape.  entries[] (may
- * be NULL) receives up to cap trials, *n_out (may be NULL) their number.
- * Synchronises the stream; walkers must be initialised.  Needs host memory
- * for one copy of the device buffers. */
+ * and in the persistent form also with the grid capped at half the resident
+ * blocks (where the memory system saturates, fewer walkers in flight can be
+ * faster); restores the walk's state before each trial and at the end, so
+ * that the walk itself is unchanged; then applies the fastest shape and, in
+ * the persistent form, its grid cap (rewl_set_grid_cap).  entries[] (may be
+ * NULL) receives up to cap trials (at most 12), *n_out (may be NULL) their
+ * number.  Synchronises the stream; walkers must be initialised.  Needs host
+ * memory for one copy of the device buffers. */
 typedef struct {
     int32_t walkers_per_block;
     int32_t residency;         /* 1: configurations in LDS, 2: in HBM        */
     int32_t persistent;        /* 1: timed with rewl_run_persistent          */
     int32_t status;            /* REWL_OK, or why the shape was not usable   */
     double ms_per_segment;     /* < 0 when not usable                        */
+    int32_t max_blocks;        /* persistent grid cap of the trial, 0 = none */
+    int32_t pad;
 } rewl_tune_entry;
 
 rewl_status rewl_autotune(rewl_ctx *ctx, int32_t segments, int32_t persistent, rewl_tune_entry *entries,
@@ -255,7 +269,8 @@ rewl_status rewl_run(rewl_ctx *ctx, int64_t n_segments);
  * round runs the exchange.  The results are bit-identical to rewl_run's.
  * The grid is as many blocks (of rewl_set_launch's walkers per block) as
  * are resident at once, at most one walker per wavefront, and at most
- * max_blocks if max_blocks > 0; *grid_out (may be NULL) receives it.  Synchronises the stream; REWL_EDEVICE if a bounded
+ * max_blocks if max_blocks > 0 (max_blocks = 0: the rewl_set_grid_cap cap,
+ * if any); *grid_out (may be NULL) receives it.  Synchronises the stream; REWL_EDEVICE if a bounded
  * device wait ran out, REWL_ERANGE if max_rounds * walkers >= 2^31 - queue
  * capacity, REWL_EUNSUPPORTED in FP64_DET mode or on explicit couplings. */
 rewl_status rewl_run_persistent(rewl_ctx *ctx, int64_t max_rounds, int32_t max_blocks, int32_t *grid_out);

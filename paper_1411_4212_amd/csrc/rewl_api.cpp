@@ -169,6 +169,7 @@ struct rewl_ctx {
     size_t off_pctl = 0, off_parr = 0, off_prnd = 0, off_pslots = 0;
     uint32_t p_cap = 0;
     int32_t last_grid = 0;
+    int32_t grid_cap = 0;        // persistent grid cap for max_blocks = 0 (0: none)
     int32_t n_walkers = 0, n_xstat = 0;
     int64_t total_bins = 0, total_spins = 0;
     int32_t lds_spins_bytes = 0, lds_bins = 0;
@@ -812,6 +813,7 @@ rewl_status rewl_run_persistent(rewl_ctx *ctx, int64_t max_rounds, int32_t max_b
     for (auto &d : ctx->idesc) seg_max = std::max<int64_t>(seg_max, d.seg_len);
     a.p_spin_limit = (uint64_t)std::min<int64_t>(std::max<int64_t>(512 * seg_max, int64_t(1) << 22), int64_t(1) << 32);
     int grid = 0;
+    if (max_blocks == 0) max_blocks = ctx->grid_cap;
     int rc = launch_persistent(a, ctx->mode, ctx->stream, ctx->lds_per_walker, n_cu, max_blocks, &grid);
     if (rc) return fail(rc, "persistent kernel launch failed");
     ctx->last_grid = grid;
@@ -843,6 +845,22 @@ rewl_status rewl_set_launch(rewl_ctx *ctx, int32_t walkers_per_block, int32_t re
         plan_launch(ctx);
         return st;
     }
+    ctx->grid_cap = 0;
+    return REWL_OK;
+}
+
+rewl_status rewl_set_grid_cap(rewl_ctx *ctx, int32_t max_blocks)
+{
+    if (!ctx) return fail(REWL_EINVAL, "null context");
+    if (max_blocks < 0) return fail(REWL_EINVAL, "negative grid cap");
+    ctx->grid_cap = max_blocks;
+    return REWL_OK;
+}
+
+rewl_status rewl_get_grid_cap(rewl_ctx *ctx, int32_t *max_blocks)
+{
+    if (!ctx || !max_blocks) return fail(REWL_EINVAL, "null argument");
+    *max_blocks = ctx->grid_cap;
     return REWL_OK;
 }
 
@@ -1310,24 +1328,46 @@ rewl_status rewl_autotune(rewl_ctx *ctx, int32_t segments, int32_t persistent, r
     Snapshot sn;
     rewl_status st = take_snapshot(ctx, sn);
     if (st) return st;
-    const int32_t old_w = ctx->wpb_req, old_r = ctx->residency_req;
+    const int32_t old_w = ctx->wpb_req, old_r = ctx->residency_req, old_cap = ctx->grid_cap;
+    ctx->grid_cap = 0;
     EventPair ev;
     HIP_TRY(hipEventCreate(&ev.a));
     HIP_TRY(hipEventCreate(&ev.b));
+    int32_t cap_blocks = 0;       // grid cap of the current trial (persistent form)
+    int32_t grid_full = 0;        // grid the uncapped trial of the same shape launched
+    bool full_ok = false;         // that trial was timed
     auto run = [&](int32_t n) -> rewl_status {
-        if (persistent) return rewl_run_persistent(ctx, n, 0, nullptr);
+        if (persistent) {
+            int32_t g = 0;
+            rewl_status s = rewl_run_persistent(ctx, n, cap_blocks, &g);
+            if (!s && cap_blocks == 0) grid_full = g;
+            return s;
+        }
         return rewl_run(ctx, n);
     };
-    int32_t n = 0, best_w = 0, best_r = 0;
+    int32_t n = 0, best_w = 0, best_r = 0, best_cap = 0;
     double best = -1.0;
     const int wpbs[3] = {1, 2, 4};
     for (int r = 1; r <= 2; ++r) {
-        for (int k = 0; k < 3; ++k) {
+        for (int kk = 0; kk < (persistent ? 6 : 3); ++kk) {
+            // persistent form: each shape with every resident block, then with
+            // the grid capped at half of what the first trial launched
+            const int k = persistent ? kk / 2 : kk;
+            const bool halved = persistent && (kk & 1);
+            if (halved) {
+                if (!full_ok || grid_full < 2) continue;
+                cap_blocks = grid_full / 2;
+            } else {
+                cap_blocks = 0;
+                grid_full = 0;
+                full_ok = false;
+            }
             rewl_tune_entry e{};
             e.walkers_per_block = wpbs[k];
             e.residency = r;
             e.persistent = persistent ? 1 : 0;
             e.ms_per_segment = -1.0;
+            e.max_blocks = cap_blocks;
             ctx->wpb_req = wpbs[k];
             ctx->residency_req = r;
             e.status = plan_launch(ctx);
@@ -1358,6 +1398,7 @@ rewl_status rewl_autotune(rewl_ctx *ctx, int32_t segments, int32_t persistent, r
                     // a failed trial leaves the walk restored and the old shape
                     ctx->wpb_req = old_w;
                     ctx->residency_req = old_r;
+                    ctx->grid_cap = old_cap;
                     plan_launch(ctx);
                     rewl_status st2 = restore_snapshot(ctx, sn);
                     return st2 ? st2 : st;
@@ -1365,10 +1406,12 @@ rewl_status rewl_autotune(rewl_ctx *ctx, int32_t segments, int32_t persistent, r
                 float ms = 0.f;
                 HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
                 e.ms_per_segment = (double)ms / segments;
+                if (!halved) full_ok = true;
                 if (best < 0.0 || e.ms_per_segment < best) {
                     best = e.ms_per_segment;
                     best_w = wpbs[k];
                     best_r = r;
+                    best_cap = cap_blocks;
                 }
             }
             if (entries && n < cap) entries[n] = e;
@@ -1380,11 +1423,13 @@ rewl_status rewl_autotune(rewl_ctx *ctx, int32_t segments, int32_t persistent, r
     if (best < 0.0) {
         ctx->wpb_req = old_w;
         ctx->residency_req = old_r;
+        ctx->grid_cap = old_cap;
         plan_launch(ctx);
         return fail(REWL_EUNSUPPORTED, "no launch shape is usable for this context");
     }
     ctx->wpb_req = best_w;
     ctx->residency_req = best_r;
+    ctx->grid_cap = persistent ? best_cap : old_cap;
     st = plan_launch(ctx);
     if (st) return st;
     if (n_out) *n_out = std::min(n, cap);

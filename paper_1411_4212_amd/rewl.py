@@ -41,7 +41,8 @@ class rewl_walker_state(C.Structure):
 
 class rewl_tune_entry(C.Structure):
     _fields_ = [("walkers_per_block", C.c_int32), ("residency", C.c_int32), ("persistent", C.c_int32),
-                ("status", C.c_int32), ("ms_per_segment", C.c_double)]
+                ("status", C.c_int32), ("ms_per_segment", C.c_double), ("max_blocks", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class RewlError(RuntimeError):
@@ -91,6 +92,8 @@ _SIGS = {
     "rewl_read_step": [_vp, _P(_i64)],
     "rewl_set_trace": [_vp, _vp, _i64],
     "rewl_set_launch": [_vp, _i32, _i32],
+    "rewl_set_grid_cap": [_vp, _i32],
+    "rewl_get_grid_cap": [_vp, _P(_i32)],
     "rewl_set_proposal": [_vp, _i32, _vp],
     "rewl_set_harvest": [_vp, _vp, _i64, _i32],
     "rewl_read_harvest_counts": [_vp, _P(_i64), _i32],
@@ -261,10 +264,10 @@ def rewl_run_persistent(ctx, max_rounds, max_blocks=0):
 
 
 def rewl_autotune(ctx, segments, persistent=False):
-    arr = (rewl_tune_entry * 6)()
+    arr = (rewl_tune_entry * 12)()
     n = _i32(0)
-    _call("rewl_autotune", ctx, segments, 1 if persistent else 0, arr, 6, C.byref(n))
-    return [{f: getattr(arr[k], f) for f, _ in rewl_tune_entry._fields_} for k in range(n.value)]
+    _call("rewl_autotune", ctx, segments, 1 if persistent else 0, arr, 12, C.byref(n))
+    return [{f: getattr(arr[k], f) for f, _ in rewl_tune_entry._fields_ if f != "pad"} for k in range(n.value)]
 
 
 def rewl_fingerprint(ctx):
@@ -319,6 +322,16 @@ def rewl_set_trace(ctx, dev_ptr, capacity):
 
 def rewl_set_launch(ctx, walkers_per_block, residency=0):
     _call("rewl_set_launch", ctx, walkers_per_block, residency)
+
+
+def rewl_set_grid_cap(ctx, max_blocks):
+    _call("rewl_set_grid_cap", ctx, max_blocks)
+
+
+def rewl_get_grid_cap(ctx):
+    g = _i32()
+    _call("rewl_get_grid_cap", ctx, C.byref(g))
+    return g.value
 
 
 def rewl_get_launch(ctx):
@@ -503,10 +516,11 @@ class Run:
         return rewl_run_persistent(self.ctx, max_rounds, max_blocks)
 
     def autotune(self, segments=2, persistent=False, cache=None):
-        """Choose walkers per block and residency by timing (the walk's state
-        is restored, so results do not change).  With `cache` (a JSON file
-        path) a shape chosen earlier for the same configuration digest is
-        applied without timing.  Returns the trials (empty when cached)."""
+        """Choose walkers per block and residency (and, for the persistent
+        kernel, a grid cap) by timing; the walk's state is restored, so
+        results do not change.  With `cache` (a JSON file path) a shape
+        chosen earlier for the same configuration digest is applied without
+        timing.  Returns the trials (empty when cached)."""
         import json
         key = "%016x/%s" % (rewl_fingerprint(self.ctx), "persistent" if persistent else "run")
         table = {}
@@ -514,13 +528,17 @@ class Run:
             with open(cache) as f:
                 table = json.load(f)
             if key in table:
-                w, r = table[key]
+                w, r = table[key][:2]
                 rewl_set_launch(self.ctx, w, r)
+                if persistent and len(table[key]) > 2:
+                    rewl_set_grid_cap(self.ctx, table[key][2])
                 return []
         trials = rewl_autotune(self.ctx, segments, persistent)
         if cache:
             lc = rewl_get_launch(self.ctx)
             table[key] = [lc["walkers_per_block"], 1 if lc["spins_in_lds"] else 2]
+            if persistent:
+                table[key].append(rewl_get_grid_cap(self.ctx))
             tmp = cache + ".tmp"
             with open(tmp, "w") as f:
                 json.dump(table, f, indent=1)
@@ -572,6 +590,13 @@ class Run:
 
     def set_launch(self, walkers_per_block, residency=0):
         rewl_set_launch(self.ctx, walkers_per_block, residency)
+
+    def grid_cap(self):
+        """Grid cap of run_persistent calls with max_blocks = 0 (0: none)."""
+        return rewl_get_grid_cap(self.ctx)
+
+    def set_grid_cap(self, max_blocks):
+        rewl_set_grid_cap(self.ctx, max_blocks)
 
     def launch(self):
         return rewl_get_launch(self.ctx)

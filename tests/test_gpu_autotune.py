@@ -1,7 +1,8 @@
 """Launch-shape autotuner (rewl_autotune): it times every usable walkers-
-per-block / residency shape, restores the walk's state around each trial,
-and applies the fastest; the walk that follows is bit-identical to one that
-never tuned (the shape does not change results).  A JSON cache keyed by the
+per-block / residency shape (the persistent form each also at half its
+grid), restores the walk's state around each trial, and applies the
+fastest; the walk that follows is bit-identical to one that never tuned
+(the shape and grid do not change results).  A JSON cache keyed by the
 configuration digest reapplies the choice without timing."""
 import os
 import sys
@@ -44,13 +45,18 @@ def test_autotune_restores_state_and_applies_fastest(persistent, tmp_path):
     cache = str(tmp_path / "tune.json")
     trials = g.autotune(segments=2, persistent=persistent, cache=cache)
     _say("trials", trials, "chosen", g.launch())
-    assert len(trials) == 6
+    full = [t for t in trials if t["max_blocks"] == 0]
+    capped = [t for t in trials if t["max_blocks"] > 0]
+    assert len(full) == 6
+    # the persistent form also times each usable shape at half its grid
+    assert len(capped) == (sum(t["status"] == 0 for t in full) if persistent else 0)
     ok = [t for t in trials if t["status"] == 0]
     assert ok and all(t["ms_per_segment"] > 0 for t in ok)
     best = min(ok, key=lambda t: t["ms_per_segment"])
     lc = g.launch()
     assert lc["walkers_per_block"] == best["walkers_per_block"]
     assert lc["spins_in_lds"] == (best["residency"] == 1)
+    assert g.grid_cap() == best["max_blocks"]
     assert _state(g, cfgs) == before
     assert g.step() == ref.step()
     ref.run(3)
@@ -63,4 +69,14 @@ def test_autotune_restores_state_and_applies_fastest(persistent, tmp_path):
     h = gpu_from(cfgs, "fp32_de")
     assert h.autotune(segments=2, persistent=persistent, cache=cache) == []
     assert h.launch() == lc
+    assert h.grid_cap() == g.grid_cap()
+    # a grid cap leaves results unchanged; rewl_set_launch clears it
+    if persistent:
+        full_grid = ref.run_persistent(2)
+        h.set_grid_cap(max(1, full_grid // 3))
+        h.run(5)
+        assert h.run_persistent(2) <= max(1, full_grid // 3)
+        assert _state(h, cfgs) == _state(ref, cfgs)
+        h.set_launch(lc["walkers_per_block"], 1 if lc["spins_in_lds"] else 2)
+        assert h.grid_cap() == 0
     assert os.path.exists(cache)
