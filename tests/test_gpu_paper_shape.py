@@ -2,8 +2,7 @@
 windows at overlap 0.75, one walker each; bcc with couplings J = (1, 0.5),
 128,000 spins, configurations in HBM, ferromagnetic start).
 
-After two segments of the look-ahead kernel, on a sample of walkers spread
-over the whole energy range:
+After two segments of the look-ahead kernel, for every walker:
   * each window's bin range is the one the oracle's window placement gives
     for this bin count, window count and overlap;
   * the running energy equals the oracle's full FP64 energy of the
@@ -44,25 +43,26 @@ def test_paper_shape_L40_energies_windows_and_persistent():
     _say("L=40: two rounds done (persistent, grid %d)" % grid)
     o = oracle.Oracle(L=L, J=J)
     seg = wl["schedule"][4]
-    sample = sorted(set(np.linspace(0, W - 1, 24).astype(int).tolist()))
     configs = []
+    worst = 0.0
     for w in range(W):
         st = g.walker(0, w)
         configs.append(st["config"])
         assert st == p.walker(0, w), w
         lo, hi = g.window(0, w)
+        assert (lo, hi) == oracle.window_bins(B, h, ov, w // m), w
         assert lo <= st["bin"] < hi
         assert st["attempts"] == 2 * seg or st["done"]
-    assert sorted(configs) == list(range(W))
-    for w in sample:
-        assert g.window(0, w) == oracle.window_bins(B, h, ov, w // m), w
-        st = g.walker(0, w)
         S = g.config(0, st["config"])
         assert np.allclose(np.linalg.norm(S, axis=1), 1.0, atol=1e-5)
         assert np.array_equal(bits(S), bits(p.config(0, st["config"])))
         Ef = o.energy(S)
-        _say("walker %3d window %s bin %d E %.4f full %.4f" % (w, g.window(0, w), st["bin"], st["E"], Ef))
         assert abs(Ef - st["E"]) <= 2e-2 * (1 + abs(Ef)) ** 0.5, (w, Ef, st["E"])
+        worst = max(worst, abs(Ef - st["E"]))
         assert np.array_equal(bits(g.lng(0, w)), bits(p.lng(0, w)))
+        if w % 128 == 0 or w == W - 1:
+            _say("walker %3d window (%d, %d) bin %d E %.4f full %.4f" % (w, lo, hi, st["bin"], st["E"], Ef))
+    assert sorted(configs) == list(range(W))
+    _say("L=40: max |E - full energy| over %d walkers %.2e" % (W, worst))
     g.close()
     p.close()
