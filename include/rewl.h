@@ -212,14 +212,15 @@ rewl_status rewl_get_launch(rewl_ctx *ctx, int32_t *walkers_per_block, int32_t *
 
 /* Launch-shape autotuner.  Times `segments` segments (rewl_run, or one
  * rewl_run_persistent call if persistent != 0) for every walkers-per-block
- * count in {1, 2, 4} and residency in {LDS, HBM} that the context can use,
- * and in the persistent form also with the grid capped at half the resident
- * blocks (where the memory system saturates, fewer walkers in flight can be
- * faster); restores the walk's state before each trial and at the end, so
- * that the walk itself is unchanged; then applies the fastest shape and, in
- * the persistent form, its grid cap (rewl_set_grid_cap).  entries[] (may be
- * NULL) receives up to cap trials (at most 12), *n_out (may be NULL) their
- * number.  Synchronises the stream; walkers must be initialised.  Needs host
+ * count in {1, 2, 4} and residency in {LDS, HBM} that the context can use.
+ * In the persistent form each shape is timed first with every resident
+ * block, then with the grid halved, a quarter, ... (down to 1/16) for as
+ * long as each step is faster than the one before (where the memory system
+ * saturates, fewer walkers in flight can be faster).  The walk's state is
+ * restored before each trial and at the end, so that the walk itself is
+ * unchanged; then the fastest shape and, in the persistent form, its grid
+ * cap (rewl_set_grid_cap) are applied.  entries[] (may be NULL) receives up
+ * to cap trials (at most 30), *n_out (may be NULL) their number.  Synchronises the stream; walkers must be initialised.  Needs host
  * memory for one copy of the device buffers. */
 typedef struct {
     int32_t walkers_per_block;

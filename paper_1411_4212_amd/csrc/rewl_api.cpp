@@ -1333,9 +1333,14 @@ rewl_status rewl_autotune(rewl_ctx *ctx, int32_t segments, int32_t persistent, r
     EventPair ev;
     HIP_TRY(hipEventCreate(&ev.a));
     HIP_TRY(hipEventCreate(&ev.b));
+    // persistent form: each shape first with every resident block, then with
+    // the grid halved again and again (at most kHalvings times) while that
+    // keeps getting faster
+    constexpr int kHalvings = 4;
     int32_t cap_blocks = 0;       // grid cap of the current trial (persistent form)
     int32_t grid_full = 0;        // grid the uncapped trial of the same shape launched
-    bool full_ok = false;         // that trial was timed
+    bool keep = false;            // the shape's last trial was timed and faster than the one before
+    double shape_ms = -1.0;       // time of the shape's last timed trial
     auto run = [&](int32_t n) -> rewl_status {
         if (persistent) {
             int32_t g = 0;
@@ -1349,19 +1354,18 @@ rewl_status rewl_autotune(rewl_ctx *ctx, int32_t segments, int32_t persistent, r
     double best = -1.0;
     const int wpbs[3] = {1, 2, 4};
     for (int r = 1; r <= 2; ++r) {
-        for (int kk = 0; kk < (persistent ? 6 : 3); ++kk) {
-            // persistent form: each shape with every resident block, then with
-            // the grid capped at half of what the first trial launched
-            const int k = persistent ? kk / 2 : kk;
-            const bool halved = persistent && (kk & 1);
-            if (halved) {
-                if (!full_ok || grid_full < 2) continue;
-                cap_blocks = grid_full / 2;
+        for (int kk = 0; kk < (persistent ? 3 * (1 + kHalvings) : 3); ++kk) {
+            const int k = persistent ? kk / (1 + kHalvings) : kk;
+            const int halvings = persistent ? kk % (1 + kHalvings) : 0;
+            if (halvings > 0) {
+                if (!keep || (grid_full >> halvings) < 1) continue;
+                cap_blocks = grid_full >> halvings;
             } else {
                 cap_blocks = 0;
                 grid_full = 0;
-                full_ok = false;
+                shape_ms = -1.0;
             }
+            keep = false;
             rewl_tune_entry e{};
             e.walkers_per_block = wpbs[k];
             e.residency = r;
@@ -1406,7 +1410,8 @@ rewl_status rewl_autotune(rewl_ctx *ctx, int32_t segments, int32_t persistent, r
                 float ms = 0.f;
                 HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
                 e.ms_per_segment = (double)ms / segments;
-                if (!halved) full_ok = true;
+                keep = shape_ms < 0.0 || e.ms_per_segment < shape_ms;
+                shape_ms = e.ms_per_segment;
                 if (best < 0.0 || e.ms_per_segment < best) {
                     best = e.ms_per_segment;
                     best_w = wpbs[k];

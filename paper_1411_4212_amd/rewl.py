@@ -264,9 +264,9 @@ def rewl_run_persistent(ctx, max_rounds, max_blocks=0):
 
 
 def rewl_autotune(ctx, segments, persistent=False):
-    arr = (rewl_tune_entry * 12)()
+    arr = (rewl_tune_entry * 32)()
     n = _i32(0)
-    _call("rewl_autotune", ctx, segments, 1 if persistent else 0, arr, 12, C.byref(n))
+    _call("rewl_autotune", ctx, segments, 1 if persistent else 0, arr, 32, C.byref(n))
     return [{f: getattr(arr[k], f) for f, _ in rewl_tune_entry._fields_ if f != "pad"} for k in range(n.value)]
 
 

@@ -1,9 +1,9 @@
 """Launch-shape autotuner (rewl_autotune): it times every usable walkers-
-per-block / residency shape (the persistent form each also at half its
-grid), restores the walk's state around each trial, and applies the
-fastest; the walk that follows is bit-identical to one that never tuned
-(the shape and grid do not change results).  A JSON cache keyed by the
-configuration digest reapplies the choice without timing."""
+per-block / residency shape (the persistent form each also at halved
+grids while that is faster), restores the walk's state around each trial,
+and applies the fastest; the walk that follows is bit-identical to one
+that never tuned (the shape and grid do not change results).  A JSON cache
+keyed by the configuration digest reapplies the choice without timing."""
 import os
 import sys
 
@@ -46,10 +46,25 @@ def test_autotune_restores_state_and_applies_fastest(persistent, tmp_path):
     trials = g.autotune(segments=2, persistent=persistent, cache=cache)
     _say("trials", trials, "chosen", g.launch())
     full = [t for t in trials if t["max_blocks"] == 0]
-    capped = [t for t in trials if t["max_blocks"] > 0]
     assert len(full) == 6
-    # the persistent form also times each usable shape at half its grid
-    assert len(capped) == (sum(t["status"] == 0 for t in full) if persistent else 0)
+    if persistent:
+        # each usable shape is also timed at half its grid, and halved again
+        # (to 1/16 at most) while each step was faster than the one before
+        for f in full:
+            shape = [t for t in trials if (t["walkers_per_block"], t["residency"]) ==
+                     (f["walkers_per_block"], f["residency"])]
+            assert shape[0] is f
+            if f["status"] != 0:
+                assert len(shape) == 1
+                continue
+            assert 2 <= len(shape) <= 5
+            caps = [t["max_blocks"] for t in shape[1:]]
+            assert all(c2 == c1 // 2 for c1, c2 in zip(caps, caps[1:]))
+            ms = [t["ms_per_segment"] for t in shape]
+            assert all(ms[i] < ms[i - 1] for i in range(1, len(ms) - 1))
+            assert len(shape) == 5 or ms[-1] >= ms[-2] or caps[-1] // 2 < 1
+    else:
+        assert len(trials) == 6
     ok = [t for t in trials if t["status"] == 0]
     assert ok and all(t["ms_per_segment"] > 0 for t in ok)
     best = min(ok, key=lambda t: t["ms_per_segment"])
