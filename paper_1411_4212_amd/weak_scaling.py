@@ -74,13 +74,20 @@ def summarize(first):
 
 
 def run_one(L, serial=False, cap_moves=2 * 10 ** 7, seg=10000, poll_segments=10, seed=0,
-            J=J_PAPER_SHAPE, bin_width=None):
+            J=J_PAPER_SHAPE, bin_width=None, proposal="uniform", harvest_segments=2,
+            max_records=10 ** 7, log=None):
     """Run REWL (or the serial walk) from the ferromagnet until every window
     has finished its first WL iteration or cap_moves trial moves per walker
     have run.  Returns per-window move counts at the first flat histogram
-    (to within poll_segments * seg moves; None where the cap came first)."""
+    (to within poll_segments * seg moves; None where the cap came first).
+    proposal="learned": the first harvest_segments segments are the plain
+    walk, recording (field, spin) pairs of every k-th move (at most about
+    max_records), on which the network is trained on the device; the walk
+    then continues with the learned proposal.  Those segments count as moves
+    of the walk."""
     import torch
-    from .rewl import Run
+    from .rewl import Run, rewl_set_harvest
+    from . import learned
     lay = layout(L, J, serial, bin_width)
     N = 2 * L ** 3
     cfg = dict(lattice=("bcc", L, list(J)),
@@ -97,22 +104,47 @@ def run_one(L, serial=False, cap_moves=2 * 10 ** 7, seg=10000, poll_segments=10,
     first = [None] * nw
     t0 = time.perf_counter()
     moves = 0
-    while moves < cap_moves:
-        r.run(poll_segments)
-        moves += poll_segments * seg
+    info = {}
+
+    def note_finished():
         for w in range(nw):
             if first[w] is None and r.walker(0, w)["iteration"] >= 1:
                 first[w] = moves
-        if all(f is not None for f in first):
-            break
+
+    if proposal == "learned":
+        every = max(1, -(-harvest_segments * seg * nw // max_records))
+        r.set_harvest(harvest_segments * seg // every + 1, every)
+        r.run(harvest_segments)
+        moves += harvest_segments * seg
+        recs = r.harvested()
+        rewl_set_harvest(r.ctx, None, 0, 1)
+        params = learned.init_params(1, recs.device)
+        losses = learned.train(recs, params, epochs=4, batch=4096, lr=2e-3, seed=3)
+        r.set_proposal(params)
+        torch.cuda.synchronize()
+        info = dict(records=int(recs.shape[0]), loss=[round(float(x), 4) for x in losses],
+                    harvest_train_seconds=round(time.perf_counter() - t0, 2))
+        del recs
+        r.harvest_buf = None
+        note_finished()
+    next_log = 10 ** 7
+    while moves < cap_moves and not all(f is not None for f in first):
+        r.run(poll_segments)
+        moves += poll_segments * seg
+        note_finished()
+        if log and moves >= next_log:
+            log("L=%d %s: %.3g moves, %d of %d windows finished, %.0f s"
+                % (L, proposal, moves, sum(f is not None for f in first), nw, time.perf_counter() - t0))
+            next_log += 10 ** 7
     seconds = time.perf_counter() - t0
     launch = r.launch()
+    acc = sum(r.walker(0, w)["accepts"] for w in range(nw)) / max(1, sum(r.walker(0, w)["attempts"] for w in range(nw)))
     r.close()
-    return dict(L=L, N=N, serial=serial, windows=lay["h"], bins=lay["bins"],
+    return dict(L=L, N=N, serial=serial, proposal=proposal, windows=lay["h"], bins=lay["bins"],
                 window_width=round(lay["width"], 2), cap_moves=cap_moves,
-                resolution_moves=poll_segments * seg, **summarize(first),
-                seconds=round(seconds, 2), init_seconds=round(t_init, 2),
-                spins_in_lds=bool(launch["spins_in_lds"]))
+                resolution_moves=poll_segments * seg, **summarize(first), first_moves=first,
+                acceptance=round(acc, 4), seconds=round(seconds, 2), init_seconds=round(t_init, 2),
+                spins_in_lds=bool(launch["spins_in_lds"]), **info)
 
 
 def main():
@@ -123,13 +155,15 @@ def main():
     ap.add_argument("--serial-cap", type=int, default=5 * 10 ** 7)
     ap.add_argument("--poll", type=int, default=10, help="segments between reads of the walker states")
     ap.add_argument("--bin-width", type=float, default=None, help="bin width in J (default: 100 bins per window)")
+    ap.add_argument("--proposal", choices=("uniform", "learned"), default="uniform")
     args = ap.parse_args()
+    log = lambda m: print(m, file=sys.stderr, flush=True)
     for L in [int(x) for x in args.serial_sizes.split(",") if x]:
         print(json.dumps(run_one(L, serial=True, cap_moves=args.serial_cap, poll_segments=args.poll,
-                                 bin_width=args.bin_width)), flush=True)
+                                 bin_width=args.bin_width, proposal=args.proposal, log=log)), flush=True)
     for L in [int(x) for x in args.sizes.split(",") if x]:
-        print(json.dumps(run_one(L, cap_moves=args.cap, poll_segments=args.poll, bin_width=args.bin_width)),
-              flush=True)
+        print(json.dumps(run_one(L, cap_moves=args.cap, poll_segments=args.poll, bin_width=args.bin_width,
+                                 proposal=args.proposal, log=log)), flush=True)
 
 
 if __name__ == "__main__":
