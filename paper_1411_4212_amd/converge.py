@@ -5,10 +5,12 @@ the joined ln g.  Library function plus a command line:
 
     python -m paper_1411_4212_amd.converge --workload c4 --cap 600
 
-The learned run starts like the plain one; once every walker has reached
-ln f <= 2^-harvest_iter it records (x, S_i) of every k-th move for a few
-segments, trains the network on the device, switches to the learned
-proposal and continues to the end.  Its time includes harvest and training.
+The learned run starts like the plain one; once the median walker has
+reached ln f <= 2^-harvest_iter (with harvest_iter <= 0: right after the
+start, while the walkers sit at the low end of their windows) it records
+(x, S_i) of every k-th move for a few segments, trains the network on the
+device, switches to the learned proposal and continues to the end.  Its
+time includes harvest and training.
 Progress goes to stdout as one JSON line per chunk.
 """
 import argparse
@@ -47,6 +49,33 @@ def run(cfg, proposal="uniform", cap_s=600.0, rounds=256, harvest_iter=8, harves
     info = {}
     done = False
     done_at = np.full(r.n_walkers, np.nan)
+
+    def switch():
+        # harvest (field, spin) pairs of the plain walk, train, switch
+        th = time.perf_counter()
+        seg = cfg["schedule"][4]
+        cap = harvest_segments * seg // harvest_every + 1
+        r.set_harvest(cap, harvest_every)
+        r.run(harvest_segments)
+        recs = r.harvested()
+        from .rewl import rewl_set_harvest
+        rewl_set_harvest(r.ctx, None, 0, 1)
+        params = learned.init_params(1, dev)
+        losses = learned.train(recs, params, epochs=epochs, batch=4096, lr=2e-3, seed=3)
+        r.set_proposal(params)
+        torch.cuda.synchronize()
+        out = dict(records=int(recs.shape[0]), loss=[round(float(x), 4) for x in losses],
+                   harvest_train_s=round(time.perf_counter() - th, 2))
+        print(json.dumps(dict(tag=tag, event="switched to learned proposal", **out)), flush=True)
+        del recs
+        r.harvest_buf = None
+        return out
+
+    if proposal == "learned" and harvest_iter <= 0:
+        # right after the start: the walkers have just entered their windows
+        # from below (ferromagnetic start), so the records cover the low end
+        info = switch()
+        phase = "learned"
     while True:
         r.run_persistent(rounds)
         done = bool(r.poll())
@@ -59,22 +88,7 @@ def run(cfg, proposal="uniform", cap_s=600.0, rounds=256, harvest_iter=8, harves
             break
         its = np.repeat(np.arange(len(p["iter_hist"])), p["iter_hist"])
         if proposal == "learned" and phase == "plain" and np.median(its) >= harvest_iter:
-            th = time.perf_counter()
-            seg = cfg["schedule"][4]
-            cap = harvest_segments * seg // harvest_every + 1
-            r.set_harvest(cap, harvest_every)
-            r.run(harvest_segments)
-            recs = r.harvested()
-            from .rewl import rewl_set_harvest
-            rewl_set_harvest(r.ctx, None, 0, 1)
-            params = learned.init_params(1, dev)
-            losses = learned.train(recs, params, epochs=epochs, batch=4096, lr=2e-3, seed=3)
-            r.set_proposal(params)
-            torch.cuda.synchronize()
-            info = dict(records=int(recs.shape[0]), loss=[round(float(x), 4) for x in losses],
-                        harvest_train_s=round(time.perf_counter() - th, 2))
-            print(json.dumps(dict(tag=tag, event="switched to learned proposal", **info)), flush=True)
-            del recs
+            info = switch()
             phase = "learned"
     seconds = time.perf_counter() - t0
     states = [r.walker(0, w) for w in range(r.n_walkers)]
