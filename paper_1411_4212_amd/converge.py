@@ -206,15 +206,31 @@ def race(cfg, proposal="uniform", R=64, chunk=8, cap_s=600.0, harvest_iter=6, ha
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="c4")
+    ap.add_argument("--workload", default="c4",
+                    help="a workloads.py configuration (c4, c5, ...), or scan_L<n>: the weak-scaling "
+                         "layout for bcc side n (one walker per window, 3 J bins, ferromagnetic start)")
     ap.add_argument("--cap", type=float, default=600.0, help="seconds per run")
     ap.add_argument("--lnf-final-exp", type=int, default=20, help="run to ln f = 2^-this")
     ap.add_argument("--proposals", default="uniform,learned")
     ap.add_argument("--seeds", default="0")
+    ap.add_argument("--harvest-iter", type=int, default=8,
+                    help="learned runs: harvest once the median walker is at ln f <= 2^-this "
+                         "(<= 0: right after the start)")
+    ap.add_argument("--harvest-segments", type=int, default=4)
+    ap.add_argument("--harvest-every", type=int, default=16)
+    ap.add_argument("--rounds", type=int, default=256, help="rounds per persistent launch")
     ap.add_argument("--out", default=None, help="write the joined ln g of every run (npz)")
     args = ap.parse_args()
     from . import workloads
-    cfg = getattr(workloads, args.workload)()
+    if args.workload.startswith("scan_L"):
+        from .weak_scaling import OVERLAP, layout
+        L = int(args.workload[len("scan_L"):])
+        lay = layout(L, bin_width=3)
+        cfg = dict(lattice=("bcc", L, [1.0, 0.5]),
+                   windows=(lay["E_min"], lay["E_max"], lay["bins"], lay["h"], OVERLAP, 1),
+                   schedule=(4, 5, 1.0, 2.0 ** -20, 10000, 100 * 2 * L ** 3), seed=0, init="ferro")
+    else:
+        cfg = getattr(workloads, args.workload)()
     s = list(cfg["schedule"])
     s[3] = 2.0 ** -args.lnf_final_exp
     cfg["schedule"] = tuple(s)
@@ -222,7 +238,9 @@ def main():
     for seed in [int(x) for x in args.seeds.split(",")]:
         for prop in args.proposals.split(","):
             tag = "%s/seed%d" % (prop, seed)
-            res, bins, lng, frags = run(cfg, prop, args.cap, seed=seed, tag=tag)
+            res, bins, lng, frags = run(cfg, prop, args.cap, rounds=args.rounds, harvest_iter=args.harvest_iter,
+                                        harvest_segments=args.harvest_segments,
+                                        harvest_every=args.harvest_every, seed=seed, tag=tag)
             results.append(res)
             curves[tag] = lng
             for k, v in frags.items():
