@@ -41,6 +41,23 @@ def test_errors_without_device():
     assert rewl.rewl_poll.__name__ == "rewl_poll"
 
 
+def test_grid_cap_calls_check_arguments_without_device():
+    """The grid-cap calls reject a null context; the autotuner's trial
+    record has the layout the header declares (4 x int32, double, 2 x int32)."""
+    import ctypes
+    from paper_1411_4212_amd import rewl
+    import pytest
+    with pytest.raises(rewl.RewlError) as e:
+        rewl.rewl_set_grid_cap(None, 4)
+    assert e.value.code == -1
+    with pytest.raises(rewl.RewlError) as e:
+        rewl.rewl_get_grid_cap(None)
+    assert e.value.code == -1
+    assert ctypes.sizeof(rewl.rewl_tune_entry) == 32
+    assert rewl.rewl_tune_entry.ms_per_segment.offset == 16
+    assert rewl.rewl_tune_entry.max_blocks.offset == 24
+
+
 def test_trace_record_layout():
     from paper_1411_4212_amd import rewl
     import oracle
