@@ -156,14 +156,16 @@ def main():
     ap.add_argument("--poll", type=int, default=10, help="segments between reads of the walker states")
     ap.add_argument("--bin-width", type=float, default=None, help="bin width in J (default: 100 bins per window)")
     ap.add_argument("--proposal", choices=("uniform", "learned"), default="uniform")
+    ap.add_argument("--seed", type=int, default=0)
     args = ap.parse_args()
     log = lambda m: print(m, file=sys.stderr, flush=True)
     for L in [int(x) for x in args.serial_sizes.split(",") if x]:
         print(json.dumps(run_one(L, serial=True, cap_moves=args.serial_cap, poll_segments=args.poll,
-                                 bin_width=args.bin_width, proposal=args.proposal, log=log)), flush=True)
+                                 bin_width=args.bin_width, proposal=args.proposal, seed=args.seed,
+                                 log=log)), flush=True)
     for L in [int(x) for x in args.sizes.split(",") if x]:
         print(json.dumps(run_one(L, cap_moves=args.cap, poll_segments=args.poll, bin_width=args.bin_width,
-                                 proposal=args.proposal, log=log)), flush=True)
+                                 proposal=args.proposal, seed=args.seed, log=log)), flush=True)
 
 
 if __name__ == "__main__":
