@@ -204,6 +204,22 @@ def race(cfg, proposal="uniform", R=64, chunk=8, cap_s=600.0, harvest_iter=6, ha
                 acceptance=acc / max(att, 1), attempts=int(att), **info), np.array(lngs)
 
 
+def workload_config(name):
+    """A workloads.py configuration by name, or "scan_L<n>": the layout of the
+    weak-scaling scan for bcc side n (J = (1, 0.5), windows of the fixed
+    width at overlap 0.75, 3 J bins, one walker per window, exchange every
+    1e4 moves, ferromagnetic start, ln f from 1 to 2^-20)."""
+    from . import workloads
+    if name.startswith("scan_L"):
+        from .weak_scaling import OVERLAP, layout
+        L = int(name[len("scan_L"):])
+        lay = layout(L, bin_width=3)
+        return dict(name=name, lattice=("bcc", L, [1.0, 0.5]),
+                    windows=(lay["E_min"], lay["E_max"], lay["bins"], lay["h"], OVERLAP, 1),
+                    schedule=(4, 5, 1.0, 2.0 ** -20, 10000, 100 * 2 * L ** 3), seed=0, init="ferro")
+    return getattr(workloads, name)()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="c4",
@@ -221,16 +237,7 @@ def main():
     ap.add_argument("--rounds", type=int, default=256, help="rounds per persistent launch")
     ap.add_argument("--out", default=None, help="write the joined ln g of every run (npz)")
     args = ap.parse_args()
-    from . import workloads
-    if args.workload.startswith("scan_L"):
-        from .weak_scaling import OVERLAP, layout
-        L = int(args.workload[len("scan_L"):])
-        lay = layout(L, bin_width=3)
-        cfg = dict(lattice=("bcc", L, [1.0, 0.5]),
-                   windows=(lay["E_min"], lay["E_max"], lay["bins"], lay["h"], OVERLAP, 1),
-                   schedule=(4, 5, 1.0, 2.0 ** -20, 10000, 100 * 2 * L ** 3), seed=0, init="ferro")
-    else:
-        cfg = getattr(workloads, args.workload)()
+    cfg = workload_config(args.workload)
     s = list(cfg["schedule"])
     s[3] = 2.0 ** -args.lnf_final_exp
     cfg["schedule"] = tuple(s)

@@ -73,6 +73,25 @@ def test_weak_scaling_layout():
     assert (s["h"], s["bins"]) == (1, 350)
 
 
+def test_scan_workload_for_convergence_runs():
+    """converge's scan_L<n> workload is the weak-scaling layout at 3 J bins:
+    the same windows (893 at L = 40), about 3 J per bin, one walker per
+    window, the ferromagnetic start; named workloads pass through."""
+    from paper_1411_4212_amd import weak_scaling as ws
+    from paper_1411_4212_amd import workloads as W
+    from paper_1411_4212_amd.converge import workload_config
+    c = workload_config("scan_L40")
+    lay = ws.layout(40, bin_width=3)
+    Emin, Emax, B, h, o, m = c["windows"]
+    assert (h, m, o) == (893, 1, ws.OVERLAP) and B == lay["bins"]
+    assert (Emin, Emax) == (lay["E_min"], lay["E_max"])
+    assert abs((Emax - Emin) / B - 3.0) < 0.05
+    assert c["lattice"] == ("bcc", 40, [1.0, 0.5]) and c["init"] == "ferro"
+    assert W.init_spins(c).shape == (2 * 40 ** 3, 3)
+    assert c["schedule"][3] == 2.0 ** -20
+    assert workload_config("c4") == W.c4()
+
+
 def test_weak_scaling_summary():
     """Quantiles count an unfinished window as infinitely slow; the tenths
     split the window index range evenly."""
