@@ -220,8 +220,9 @@ rewl_status rewl_get_launch(rewl_ctx *ctx, int32_t *walkers_per_block, int32_t *
  * restored before each trial and at the end, so that the walk itself is
  * unchanged; then the fastest shape and, in the persistent form, its grid
  * cap (rewl_set_grid_cap) are applied.  entries[] (may be NULL) receives up
- * to cap trials (at most 30), *n_out (may be NULL) their number.  Synchronises the stream; walkers must be initialised.  Needs host
- * memory for one copy of the device buffers. */
+ * to cap trials (at most 30), *n_out (may be NULL) their number.
+ * Synchronises the stream; walkers must be initialised.  Needs host memory
+ * for one copy of the device buffers. */
 typedef struct {
     int32_t walkers_per_block;
     int32_t residency;         /* 1: configurations in LDS, 2: in HBM        */
@@ -271,9 +272,10 @@ rewl_status rewl_run(rewl_ctx *ctx, int64_t n_segments);
  * The grid is as many blocks (of rewl_set_launch's walkers per block) as
  * are resident at once, at most one walker per wavefront, and at most
  * max_blocks if max_blocks > 0 (max_blocks = 0: the rewl_set_grid_cap cap,
- * if any); *grid_out (may be NULL) receives it.  Synchronises the stream; REWL_EDEVICE if a bounded
- * device wait ran out, REWL_ERANGE if max_rounds * walkers >= 2^31 - queue
- * capacity, REWL_EUNSUPPORTED in FP64_DET mode or on explicit couplings. */
+ * if any); *grid_out (may be NULL) receives it.  Synchronises the stream;
+ * REWL_EDEVICE if a bounded device wait ran out, REWL_ERANGE if
+ * max_rounds * walkers >= 2^31 - queue capacity, REWL_EUNSUPPORTED in
+ * FP64_DET mode or on explicit couplings. */
 rewl_status rewl_run_persistent(rewl_ctx *ctx, int64_t max_rounds, int32_t max_blocks, int32_t *grid_out);
 
 /* Enqueue the trial-move part of one segment only: exchange_interval trial
